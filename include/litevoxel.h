@@ -1,0 +1,247 @@
+/*
+ * litevoxel.h -- C-ABI of the MI355X (gfx950) differentiable sparse-voxel tile
+ * rasterizer: the hot path of the LiteVoxel training loop
+ * (arXiv 2511.02510, "LiteVoxel: Low-memory Intelligent Thresholding for
+ * Efficient Voxel Rasterization").
+ *
+ * The problem each call solves is the paper's Sec. III ("Preliminaries"):
+ *   - a pinhole camera with centre o casts one ray r(t) = o + t d(x, y),
+ *     t >= 0, through the centre of every pixel (eq. 1);
+ *   - the scene is a set of non-overlapping cube voxels, leaves of an octree
+ *     (Sec. III, "Sparse Voxel/Octree Indexing"); a leaf at level l with
+ *     integer cell coordinates (i, j, k) is the cube
+ *        [root_min + (i, j, k) e, root_min + (i + 1, j + 1, k + 1) e],
+ *        e = root_size * 2^-l;
+ *   - the voxels met by a ray are composited front to back (eq. 2-4):
+ *        T_0 = 1, w_k = T_{k-1} alpha_k, T_k = T_{k-1}(1 - alpha_k),
+ *        C = sum_k w_k c_k  (+ T_K * bg);
+ *     alpha_k = 1 - exp(-tau_k), tau_k = the integral over the chord of the
+ *     trilinear interpolation of the voxel's 8 corner densities;
+ *     c_k = max(0, sh_0 + sum_{l>=1,m} Y_lm(dir) sh_lm), a real spherical
+ *     harmonic expansion of degree <= 3 evaluated at the direction from the
+ *     camera centre to the voxel centre (constant term in colour units);
+ *     depth D = sum_k w_k (t_in + t_out)/2, alpha A = 1 - T_K;
+ *   - the per-voxel maximum blending weight
+ *        w_max(v) = max over rays hitting v of T_{k(v,r)-1} alpha_v   (eq. 5).
+ * The backward pass gives the gradient of a loss with respect to the corner
+ * densities and SH coefficients (densities and colours are the trainable
+ * voxel parameters, Sec. II-B).  lv_lf_weight / lv_l1_grad implement the
+ * inverse-Sobel reweighted L1 photometric term (Sec. IV-B, eq. 7-10) and
+ * lv_depth_quantile the depth-binned w_max quantile cutoff
+ * (Sec. IV-C, eq. 11-12 with the eq. 14 depth normalisation).
+ *
+ * Conventions for every call:
+ *   - Device pointers point to memory of the context's device, owned by the
+ *     caller; the library never frees or keeps them beyond the call, except
+ *     the workspace, whose contents lv_forward leaves for lv_backward.
+ *   - All device work is enqueued on the given stream; no call below
+ *     synchronises except lv_check_overflow, lv_export_bins, lv_autotune
+ *     and lv_read_timings, which say so.  The enqueuing calls allocate no
+ *     device memory and can be captured into a HIP graph.
+ *   - Errors: every call returns an lv_status.  Argument errors are detected
+ *     on the host before anything is enqueued (LV_ERR_ARG); a HIP runtime or
+ *     launch failure gives LV_ERR_HIP.  lv_last_error() returns a message for
+ *     the last failure on a context.  No exception crosses the ABI.
+ *   - A context is not thread-safe; use one context per host thread/stream.
+ *   - Limits: n < 2^28 voxels, n_views <= LV_MAX_VIEWS, width and height
+ *     <= 32767, levels <= 12, sh_degree <= 3, pair_capacity < 2^32.
+ *   - Preconditions documented, not checked: corner densities >= 0, leaves do
+ *     not overlap, cams_dev[i] has the width/height of cams_host[i], and
+ *     wmax holds non-negative values (not -0.0).
+ */
+#ifndef LITEVOXEL_H
+#define LITEVOXEL_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LV_MAX_VIEWS 256
+#define LV_MAX_LEVEL 12
+
+typedef enum {
+  LV_OK = 0,
+  LV_ERR_ARG = 1,          /* invalid argument (host-detected, nothing enqueued) */
+  LV_ERR_HIP = 2,          /* HIP runtime / launch failure */
+  LV_ERR_CAPACITY = 3,     /* pair buffer too small (see lv_check_overflow) */
+  LV_ERR_UNSUPPORTED = 4,  /* unsupported setting or device */
+  LV_ERR_STATE = 5         /* call out of order (e.g. graph replay without capture) */
+} lv_status;
+
+typedef struct lv_context lv_context;  /* opaque, library-owned */
+
+/* Pinhole camera (eq. 1).  OpenCV axes: x right, y down, z forward;
+ * x_cam = R (x_world - o); R row-major.  Pixel (px, py) has its centre at
+ * (px + 0.5, py + 0.5); its ray direction is
+ * normalize(R^T ((px + 0.5 - cx)/fx, (py + 0.5 - cy)/fy, 1)). */
+typedef struct {
+  float R[9];
+  float o[3];
+  float fx, fy, cx, cy;
+  int32_t width, height;
+} lv_camera;
+
+/* Sparse voxel leaves, structure of arrays in device memory. */
+typedef struct {
+  int64_t n;               /* number of leaves */
+  int32_t sh_degree;       /* 0..3 */
+  float root_min[3];       /* min corner of the cubic root cell */
+  float root_size;         /* edge of the root cell */
+  const uint16_t* ijk;     /* [3][n] integer cell coordinates at the leaf's level */
+  const uint8_t* level;    /* [n] octree level (<= 12) */
+  const float* density;    /* [8][n] corner densities, corner c = x + 2y + 4z bits */
+  const float* sh;         /* [3 (deg+1)^2][n], row (i*3 + channel), i = l*l + l + m */
+} lv_voxels;
+
+/* A batch of views rendered in one call.  Pixel buffers pack the views in
+ * order: view v starts at pixel offset off[v] = sum_{u<v} W_u H_u; rgb is
+ * [3][H][W] per view starting at 3*off[v]; depth/alpha are [H][W] per view
+ * starting at off[v]. */
+typedef struct {
+  int32_t n_views;
+  const lv_camera* cams_host;  /* host array [n_views] (sizes used for planning) */
+  const lv_camera* cams_dev;   /* device array [n_views] read by the kernels */
+  float bg[3];                 /* background colour added with weight T_K */
+} lv_frame;
+
+typedef struct {
+  int32_t tile;            /* tile side in pixels: 8, 16 or 32 */
+  int32_t chunk;           /* voxels staged in LDS per step: 64, 128 or 256 */
+  float t_eps;             /* a ray stops once T < t_eps (0 < t_eps <= 1e-5) */
+  uint64_t pair_capacity;  /* capacity of the (tile, voxel) pair buffers */
+} lv_settings;
+
+/* Execution phases timed by lv_set_timing / lv_read_timings. */
+typedef enum {
+  LV_PH_SETUP = 0, LV_PH_PREPROCESS, LV_PH_SCAN, LV_PH_EMIT, LV_PH_SORT, LV_PH_ORDER,
+  LV_PH_COMPOSITE_FWD, LV_PH_BWD_SETUP, LV_PH_COMPOSITE_BWD, LV_PH_SH_BWD,
+  LV_PH_COUNT
+} lv_phase;
+
+/* ---------------------------------------------------------------- context */
+lv_status lv_create(lv_context** out, int hip_device);   /* sets the device current */
+void lv_destroy(lv_context* ctx);
+const char* lv_status_str(lv_status s);
+const char* lv_last_error(const lv_context* ctx);        /* "" if none; ctx may be NULL */
+void lv_default_settings(lv_settings* s);                 /* tile 16, chunk 64, t_eps 1e-6 */
+
+/* Host-only argument checks (no device access): LV_OK or LV_ERR_ARG. */
+lv_status lv_validate(const lv_voxels* vox, const lv_frame* frame, const lv_settings* st);
+
+/* Host-only planning: bytes of device workspace lv_forward/lv_backward need
+ * for these shapes and settings (capacity included).  ctx may be NULL. */
+lv_status lv_query_sizes(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
+                         const lv_settings* st, uint64_t* workspace_bytes);
+
+/* ------------------------------------------------------------------ forward
+ * Sec. III, eq. 1-5.  Projects and bins every (voxel, view) record into
+ * tiles, sorts each tile's list front to back, composites every pixel and
+ * max-accumulates w_max.  Outputs: rgb [3P] (layout above), depth [P],
+ * alpha [P] (all overwritten), wmax [n] (max-combined with its contents: the
+ * caller zeroes it at the start of an adaptation window).  The workspace
+ * (>= lv_query_sizes bytes, 256-byte aligned) keeps the tile lists and the
+ * per-pixel state (index of the last hit and transmittance before it) for
+ * lv_backward.  If the pairs exceed pair_capacity the outputs are invalid
+ * and lv_check_overflow reports it. */
+lv_status lv_forward(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
+                     const lv_settings* st, void* workspace, float* rgb, float* depth,
+                     float* alpha, float* wmax, hipStream_t stream);
+
+/* ----------------------------------------------------------------- backward
+ * Adjoint of eq. 2-4 (and of the trilinear opacity and SH colour models):
+ * given dL/d(rgb) [3P] and optional dL/d(depth), dL/d(alpha) [P] (NULL =
+ * zero), writes dL/d(density) [8][n] and dL/d(sh) [3 (deg+1)^2][n]
+ * (overwritten).  Transmittance is recomputed back to front from the state
+ * lv_forward left in the workspace (same vox/frame/settings/workspace). */
+lv_status lv_backward(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
+                      const lv_settings* st, void* workspace, const float* d_rgb,
+                      const float* d_depth, const float* d_alpha, float* d_density,
+                      float* d_sh, hipStream_t stream);
+
+/* Synchronises the stream and reports the number of (tile, voxel) pairs the
+ * last lv_forward produced: LV_OK if it fitted, LV_ERR_CAPACITY otherwise. */
+lv_status lv_check_overflow(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
+                            const lv_settings* st, const void* workspace,
+                            uint64_t* pairs_needed, hipStream_t stream);
+
+/* Copies the binning state of the last lv_forward to host buffers
+ * (synchronises): tile_start [T+1] (T = total tiles, views in order,
+ * row-major), ids [tile_start[T]] voxel ids in per-tile front-to-back order,
+ * codes [n_views*n] 36-bit visibility codes, rects [n_views*n*4] pixel-centre
+ * ranges (x0, x1, y0, y1) and vis [n_views*n] (1 = record binned).  Any
+ * pointer may be NULL.  For tests and debugging. */
+lv_status lv_export_bins(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
+                         const lv_settings* st, const void* workspace, uint32_t* tile_start,
+                         uint32_t* ids, uint64_t* codes, int32_t* rects, uint8_t* vis,
+                         hipStream_t stream);
+
+/* ------------------------------------------------------------- loss (eq. 7-10)
+ * Inverse-Sobel weight of each view's target (stop-gradient, Sec. IV-B):
+ * grey = mean RGB; g = |3x3 Sobel| with replicated borders; g99 = the
+ * ceil(0.99 |P|)-th smallest g of the view; form 0 (eq. 7):
+ * w = (eps + 1 - min(1, g/g99))^gamma; form 1: w = (1 + g/g99)^-gamma
+ * (g/g99 := 0 when g99 = 0); then w~ = w / mean_view(w) (eq. 8).
+ * target/weight use the pixel layout above.  workspace >= lv_lf_weight_workspace_size. */
+uint64_t lv_lf_weight_workspace_size(int32_t n_views);
+lv_status lv_lf_weight(lv_context* ctx, const lv_frame* frame, const float* target,
+                       float gamma, int32_t form, float eps, float* weight, void* workspace,
+                       hipStream_t stream);
+
+/* Weighted L1 (eq. 10 with rho = mean over channels of |r|): writes
+ * loss[v] = (1/|P_v|) sum_p w~(p) (1/3) sum_ch |C - I| per view (device
+ * [n_views], overwritten) and d_rgb = w~ sign(C - I) / (3 |P_v|). */
+lv_status lv_l1_grad(lv_context* ctx, const lv_frame* frame, const float* rgb,
+                     const float* target, const float* weight, float* loss, float* d_rgb,
+                     hipStream_t stream);
+
+/* Piecewise-linear LF emphasis ramp gamma(t) of eq. 9 (host function). */
+float lv_gamma_schedule(float t, float total, float t0_frac, float t1_frac, float gamma_max);
+
+/* ------------------------------------------------- depth quantile (eq. 11-12)
+ * Per voxel: delta = min over views with z_c > 0 of z_c / fx (the inter-ray
+ * spacing at the voxel centre, the depth proxy), +inf if no view has it in
+ * front; z~ = clip((delta - p5)/(p95 - p5), 0, 1) with nearest-rank 5th/95th
+ * percentiles over all voxels (eq. 14); bin = min(B-1, floor(B z~)) (+inf ->
+ * B-1; all finite voxels in bin 0 if p95 <= p5 or p95 = +inf).  Binning
+ * arithmetic is binary32 in the order written.  Per bin:
+ * tau_b = the ceil(q |V_b|)-th smallest w_max (eq. 11-12; -inf if empty)
+ * and prune_v = (w_max_v <= tau_{bin(v)}).  Outputs tau [n_bins], prune [n],
+ * bins [n] (nullable).  workspace >= lv_quantile_workspace_size. */
+uint64_t lv_quantile_workspace_size(int64_t n, int32_t n_bins);
+lv_status lv_depth_quantile(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
+                            const float* wmax, int32_t n_bins, double q, void* workspace,
+                            float* tau, uint8_t* prune, uint8_t* bins, hipStream_t stream);
+
+/* ------------------------------------------------------ execution structure
+ * Graph capture: between lv_graph_begin and lv_graph_end every call that
+ * enqueues on `stream` is recorded instead of run; lv_graph_launch replays
+ * the instantiated graph on a stream.  Buffers and sizes are frozen at
+ * capture; camera poses may change between replays through cams_dev.
+ * `stream` must not be the null stream. */
+lv_status lv_graph_begin(lv_context* ctx, hipStream_t stream);
+lv_status lv_graph_end(lv_context* ctx, hipStream_t stream);
+lv_status lv_graph_launch(lv_context* ctx, hipStream_t stream);
+lv_status lv_graph_reset(lv_context* ctx);
+
+/* Autotuner: times forward+backward for every tile in {8,16,32} x chunk in
+ * {64,128,256} on these inputs (device memory it needs is allocated and freed
+ * inside; synchronises) and writes the fastest into *best (capacity sized
+ * for that tile).  ms_table (nullable) receives 9 fwd+bwd times in ms,
+ * tile-major; a configuration that cannot run gets a negative entry. */
+lv_status lv_autotune(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
+                      int32_t reps, lv_settings* best, float* ms_table, hipStream_t stream);
+
+/* Per-phase GPU timing with HIP events recorded on the call's stream.
+ * lv_read_timings synchronises and adds the elapsed ms of every phase since
+ * the last read into ms[LV_PH_COUNT] and launch counts into calls. */
+lv_status lv_set_timing(lv_context* ctx, int32_t enable);
+lv_status lv_read_timings(lv_context* ctx, double* ms, int64_t* calls);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LITEVOXEL_H */

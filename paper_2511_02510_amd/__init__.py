@@ -1,0 +1,9 @@
+"""MI355X (gfx950) differentiable sparse-voxel tile rasterizer: the hot path of
+the LiteVoxel training loop (arXiv 2511.02510), behind the C-ABI declared in
+include/litevoxel.h.  The HIP library must be built (there is no fallback)."""
+from .raster import (  # noqa: F401
+    Context, Voxels, Frame, Renderer, RasterizeFn, LiteVoxelError, rasterize, settings,
+    query_sizes, forward, backward, check_overflow, export_bins, lf_weight_workspace_size,
+    lf_weight, l1_grad, gamma_schedule, quantile_workspace_size, depth_quantile, graph_begin,
+    graph_end, graph_launch, graph_reset, autotune, set_timing, read_timings,
+)

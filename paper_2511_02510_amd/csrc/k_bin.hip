@@ -1,0 +1,483 @@
+// Projection, tile binning and per-tile front-to-back sort (gfx950).
+//
+// One (view, voxel) record per voxel and view: the voxel's 8 corners are
+// projected with a fixed binary32 operation sequence, the pixels whose centre
+// lies in the projected box are its coverage, and it is binned into every
+// TS x TS tile that coverage touches.  Each tile's list is then sorted by a
+// 36-bit visibility code: the voxel's octree path with every child bit
+// flipped where the camera centre lies above that split plane, which orders
+// any set of non-overlapping leaves front to back along every ray from the
+// camera (the order eq. 2-4 composite in).
+#include "lv_common.h"
+
+namespace lv {
+
+// ------------------------------------------------------------------ setup
+__global__ void k_setup(RasterArgs a) {
+  const int t = threadIdx.x;
+  if (t < kCounterWords) a.ws.counters[t] = 0u;
+  if (t == 0) {
+    uint32_t tb = 0;
+    uint64_t pb = 0;
+    for (int v = 0; v < a.V; ++v) {
+      const int W = a.cams[v].width, H = a.cams[v].height;
+      ViewTab vt;
+      vt.tile_base = tb;
+      vt.tiles_x = uint32_t((W + a.TS - 1) / a.TS);
+      vt.tiles_y = uint32_t((H + a.TS - 1) / a.TS);
+      vt.W = W;
+      vt.H = H;
+      vt.pad = 0;
+      vt.pix_base = pb;
+      a.ws.views[v] = vt;
+      tb += vt.tiles_x * vt.tiles_y;
+      pb += uint64_t(W) * uint64_t(H);
+    }
+  }
+}
+
+hipError_t launch_setup(const RasterArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_setup, dim3(1), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
+  uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  for (; i < n; i += stride) p[i] = v;
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  uint64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_fill_u32, dim3(uint32_t(blocks)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------- preprocess
+// One thread per voxel; the voxel's parameters are read once (coalesced SoA)
+// and every view is processed from registers.
+template <int DEG>
+__global__ __launch_bounds__(256) void k_preprocess(RasterArgs a) {
+  constexpr int NB = (DEG + 1) * (DEG + 1);
+  const int64_t n = a.n;
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int l = a.level[i];
+  const float e = ldexpf(a.root_size, -l);
+  const uint32_t ix = a.ijk[i], iy = a.ijk[n + i], iz = a.ijk[2 * n + i];
+  float b[3];
+  b[0] = a.root_min[0] + float(ix) * e;
+  b[1] = a.root_min[1] + float(iy) * e;
+  b[2] = a.root_min[2] + float(iz) * e;
+  float sg[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) sg[c] = a.density[c * n + i];
+  VoxRec vr;
+  vr.be = make_float4(b[0], b[1], b[2], e);
+  vr.s0 = make_float4(sg[0], sg[1], sg[2], sg[3]);
+  vr.s1 = make_float4(sg[4], sg[5], sg[6], sg[7]);
+  a.ws.vox[i] = vr;
+
+  float k[NB][3];
+#pragma unroll
+  for (int j = 0; j < NB; ++j)
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) k[j][ch] = a.sh[(j * 3 + ch) * n + i];
+
+  const float half_e = 0.5f * e;
+  const float xv0 = b[0] + half_e, xv1 = b[1] + half_e, xv2 = b[2] + half_e;
+  const int sh_ts = __builtin_ctz(uint32_t(a.TS));
+
+  for (int v = 0; v < a.V; ++v) {
+    const lv_camera& cam = a.cams[v];
+    const float R0 = cam.R[0], R1 = cam.R[1], R2 = cam.R[2];
+    const float R3 = cam.R[3], R4 = cam.R[4], R5 = cam.R[5];
+    const float R6 = cam.R[6], R7 = cam.R[7], R8 = cam.R[8];
+    const float o0 = cam.o[0], o1 = cam.o[1], o2 = cam.o[2];
+    const int W = cam.width, H = cam.height;
+    // --- binary32 projection of the 8 corners (no contraction, fixed order)
+    float u0 = INFINITY, u1 = -INFINITY, v0 = INFINITY, v1 = -INFINITY;
+    int near_cnt = 0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const float p0 = (c & 1) ? b[0] + e : b[0];
+      const float p1 = (c & 2) ? b[1] + e : b[1];
+      const float p2 = (c & 4) ? b[2] + e : b[2];
+      const float q0 = p0 - o0, q1 = p1 - o1, q2 = p2 - o2;
+      float xc = R0 * q0 + R1 * q1;
+      xc = xc + R2 * q2;
+      float yc = R3 * q0 + R4 * q1;
+      yc = yc + R5 * q2;
+      float zc = R6 * q0 + R7 * q1;
+      zc = zc + R8 * q2;
+      if (zc <= kZNear) {
+        ++near_cnt;
+      } else {
+        const float qx = xc / zc, qy = yc / zc;
+        const float uu = cam.fx * qx + cam.cx;
+        const float vv = cam.fy * qy + cam.cy;
+        u0 = fminf(u0, uu); u1 = fmaxf(u1, uu);
+        v0 = fminf(v0, vv); v1 = fmaxf(v1, vv);
+      }
+    }
+    Rec rec;
+    rec.r = rec.g = rec.b = 0.0f;
+    rec.flags = 0u;
+    rec.xr = rec.yr = 0u;
+    rec.code_lo = rec.code_hi = 0u;
+    bool visible = false;
+    float fx0 = 0.0f, fx1 = 0.0f, fy0 = 0.0f, fy1 = 0.0f;
+    if (near_cnt < 8) {
+      if (near_cnt > 0) {
+        fx0 = 0.0f; fx1 = float(W - 1); fy0 = 0.0f; fy1 = float(H - 1);
+        visible = true;
+      } else {
+        fx0 = ceilf(u0 - 0.5f); fx1 = floorf(u1 - 0.5f);
+        fy0 = ceilf(v0 - 0.5f); fy1 = floorf(v1 - 0.5f);
+        fx0 = fmaxf(fx0, 0.0f); fy0 = fmaxf(fy0, 0.0f);
+        fx1 = fminf(fx1, float(W - 1)); fy1 = fminf(fy1, float(H - 1));
+        visible = !(fx0 > fx1 || fy0 > fy1);
+      }
+    }
+    if (visible) {
+      const uint32_t x0 = uint32_t(fx0), x1 = uint32_t(fx1);
+      const uint32_t y0 = uint32_t(fy0), y1 = uint32_t(fy1);
+      rec.xr = x0 | (x1 << 16);
+      rec.yr = y0 | (y1 << 16);
+      // --- visibility code: flipped octree path, 3 bits per level
+      uint64_t code = 0;
+      const uint32_t idx3[3] = {ix, iy, iz};
+      const float oo[3] = {o0, o1, o2};
+      for (int m = 1; m <= l; ++m) {
+        const float half = ldexpf(a.root_size, -m);
+        uint32_t bits = 0;
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+          const uint32_t id_m = idx3[ax] >> (l - m);
+          const uint32_t child = id_m & 1u;
+          const uint32_t parent = id_m >> 1;
+          float plane = float(2u * parent + 1u) * half;
+          plane = a.root_min[ax] + plane;
+          const uint32_t flip = oo[ax] > plane ? 1u : 0u;
+          bits |= (child ^ flip) << ax;
+        }
+        code |= uint64_t(bits) << (3 * (kLMax - m));
+      }
+      rec.code_lo = uint32_t(code);
+      rec.code_hi = uint32_t(code >> 32);
+      // --- colour: SH at the direction camera -> voxel centre
+      float dx = xv0 - o0, dy = xv1 - o1, dz = xv2 - o2;
+      const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+      dx *= inv; dy *= inv; dz *= inv;
+      float Y[16];
+      sh_basis<DEG>(dx, dy, dz, Y);
+      float col[3];
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        float s = k[0][ch];
+#pragma unroll
+        for (int j = 1; j < NB; ++j) s = fmaf(Y[j], k[j][ch], s);
+        col[ch] = s;
+      }
+      uint32_t fl = 8u;
+      fl |= col[0] > 0.0f ? 1u : 0u;
+      fl |= col[1] > 0.0f ? 2u : 0u;
+      fl |= col[2] > 0.0f ? 4u : 0u;
+      rec.flags = fl;
+      rec.r = fmaxf(col[0], 0.0f);
+      rec.g = fmaxf(col[1], 0.0f);
+      rec.b = fmaxf(col[2], 0.0f);
+      // --- tile counts
+      const ViewTab vt = a.ws.views[v];
+      const uint32_t tx0 = x0 >> sh_ts, tx1 = x1 >> sh_ts;
+      const uint32_t ty0 = y0 >> sh_ts, ty1 = y1 >> sh_ts;
+      for (uint32_t ty = ty0; ty <= ty1; ++ty)
+        for (uint32_t tx = tx0; tx <= tx1; ++tx)
+          atomicAdd(&a.ws.tcount[vt.tile_base + ty * vt.tiles_x + tx], 1u);
+    }
+    uint4* dst = reinterpret_cast<uint4*>(&a.ws.rec[size_t(v) * size_t(n) + size_t(i)]);
+    dst[0] = make_uint4(__float_as_uint(rec.r), __float_as_uint(rec.g), __float_as_uint(rec.b),
+                        rec.flags);
+    dst[1] = make_uint4(rec.xr, rec.yr, rec.code_lo, rec.code_hi);
+  }
+}
+
+hipError_t launch_preprocess(const RasterArgs& a, hipStream_t s) {
+  const uint32_t blocks = uint32_t((a.n + 255) / 256);
+  if (blocks == 0) return hipSuccess;
+  switch (a.deg) {
+    case 0: hipLaunchKernelGGL(k_preprocess<0>, dim3(blocks), dim3(256), 0, s, a); break;
+    case 1: hipLaunchKernelGGL(k_preprocess<1>, dim3(blocks), dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL(k_preprocess<2>, dim3(blocks), dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL(k_preprocess<3>, dim3(blocks), dim3(256), 0, s, a); break;
+  }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------- tile scan
+// Exclusive prefix sum of the per-tile counts -> tile_start (saturating at
+// 2^32 - 1), the total pair count and the overflow flag; resets the fill
+// cursors.
+__device__ __forceinline__ unsigned long long wave_incl_scan(unsigned long long x) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    unsigned long long y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  return x;
+}
+
+// inclusive scan over a 1024-thread block; returns the block total in *tot
+__device__ unsigned long long block_incl_scan(unsigned long long x, unsigned long long* tot) {
+  __shared__ unsigned long long s_w[16];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  x = wave_incl_scan(x);
+  if (lane == 63) s_w[w] = x;
+  __syncthreads();
+  if (w == 0) {
+    unsigned long long y = lane < nw ? s_w[lane] : 0ull;
+    y = wave_incl_scan(y);
+    if (lane < nw) s_w[lane] = y;
+  }
+  __syncthreads();
+  if (w > 0) x += s_w[w - 1];
+  *tot = s_w[nw - 1];
+  __syncthreads();
+  return x;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_reduce(RasterArgs a) {
+  const uint64_t t = uint64_t(blockIdx.x) * kScanBlock + threadIdx.x;
+  unsigned long long x = t < a.T ? a.ws.tcount[t] : 0u;
+  unsigned long long tot;
+  block_incl_scan(x, &tot);
+  if (threadIdx.x == 0) reinterpret_cast<unsigned long long*>(a.ws.bsum)[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_top(RasterArgs a, uint32_t nblk) {
+  unsigned long long* bs = reinterpret_cast<unsigned long long*>(a.ws.bsum);
+  unsigned long long carry = 0;
+  for (uint32_t base = 0; base < nblk; base += kScanBlock) {
+    const uint32_t j = base + threadIdx.x;
+    unsigned long long x = j < nblk ? bs[j] : 0ull;
+    unsigned long long tot;
+    unsigned long long inc = block_incl_scan(x, &tot);
+    if (j < nblk) bs[j] = carry + inc - x;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) {
+    a.ws.counters[C_PAIRS] = carry > 0xFFFFFFFFull ? 0xFFFFFFFFu : uint32_t(carry);
+    a.ws.counters[C_OVERFLOW] = carry > a.cap ? 1u : 0u;
+  }
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_down(RasterArgs a) {
+  const uint64_t t = uint64_t(blockIdx.x) * kScanBlock + threadIdx.x;
+  unsigned long long x = t < a.T ? a.ws.tcount[t] : 0u;
+  unsigned long long tot;
+  unsigned long long inc = block_incl_scan(x, &tot);
+  const unsigned long long ex =
+      reinterpret_cast<const unsigned long long*>(a.ws.bsum)[blockIdx.x] + inc - x;
+  if (t <= a.T) {
+    a.ws.tstart[t] = ex > 0xFFFFFFFFull ? 0xFFFFFFFFu : uint32_t(ex);
+    a.ws.tfill[t] = 0u;
+  }
+}
+
+hipError_t launch_scan_tiles(const RasterArgs& a, uint32_t nblk, hipStream_t s) {
+  hipLaunchKernelGGL(k_scan_reduce, dim3(nblk), dim3(kScanBlock), 0, s, a);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanBlock), 0, s, a, nblk);
+  hipLaunchKernelGGL(k_scan_down, dim3(nblk), dim3(kScanBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ emit
+// One thread per (view, voxel) record: writes key = code << 28 | voxel id at
+// tile_start[tile] + slot for every tile the record covers (slots come from
+// an atomic cursor, so the order within a tile is fixed later by the sort).
+__global__ __launch_bounds__(256) void k_emit(RasterArgs a) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int v = blockIdx.y;
+  if (i >= a.n) return;
+  const uint4 r1 = reinterpret_cast<const uint4*>(&a.ws.rec[size_t(v) * size_t(a.n) + size_t(i)])[1];
+  const uint32_t flags =
+      reinterpret_cast<const uint4*>(&a.ws.rec[size_t(v) * size_t(a.n) + size_t(i)])[0].w;
+  if (!(flags & 8u)) return;
+  const int sh_ts = __builtin_ctz(uint32_t(a.TS));
+  const uint32_t x0 = r1.x & 0xFFFFu, x1 = r1.x >> 16, y0 = r1.y & 0xFFFFu, y1 = r1.y >> 16;
+  const unsigned long long code = (unsigned long long)r1.z | ((unsigned long long)r1.w << 32);
+  const unsigned long long key = (code << kIdBits) | (unsigned long long)i;
+  const ViewTab vt = a.ws.views[v];
+  for (uint32_t ty = (y0 >> sh_ts); ty <= (y1 >> sh_ts); ++ty)
+    for (uint32_t tx = (x0 >> sh_ts); tx <= (x1 >> sh_ts); ++tx) {
+      const uint32_t gt = vt.tile_base + ty * vt.tiles_x + tx;
+      const uint32_t slot = atomicAdd(&a.ws.tfill[gt], 1u);
+      const uint64_t pos = uint64_t(a.ws.tstart[gt]) + slot;
+      if (pos < a.cap) a.ws.pairs[pos] = key;
+    }
+}
+
+hipError_t launch_emit(const RasterArgs& a, hipStream_t s) {
+  const uint32_t bx = uint32_t((a.n + 255) / 256);
+  if (bx == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_emit, dim3(bx, a.V), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ tile order
+// Persistent composite kernels pop tiles longest list first: tiles are
+// counting-sorted by floor(log2(count)) (bucket 0 = empty), descending.
+__device__ __forceinline__ uint32_t tile_len(const RasterArgs& a, uint32_t t) {
+  const uint64_t s0 = a.ws.tstart[t] < a.cap ? a.ws.tstart[t] : a.cap;
+  const uint64_t s1 = a.ws.tstart[t + 1] < a.cap ? a.ws.tstart[t + 1] : a.cap;
+  return uint32_t(s1 - s0);
+}
+
+__device__ __forceinline__ int len_bucket(uint32_t c) {
+  if (c == 0) return 0;
+  int b = 1 + (31 - __clz(c));
+  return b > 31 ? 31 : b;
+}
+
+__global__ __launch_bounds__(256) void k_order_hist(RasterArgs a) {
+  __shared__ uint32_t h[32];
+  if (threadIdx.x < 32) h[threadIdx.x] = 0;
+  __syncthreads();
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < a.T) atomicAdd(&h[len_bucket(tile_len(a, t))], 1u);
+  __syncthreads();
+  if (threadIdx.x < 32 && h[threadIdx.x]) atomicAdd(&a.ws.counters[C_BUCKET + threadIdx.x], h[threadIdx.x]);
+}
+
+__global__ void k_order_scan(RasterArgs a) {
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (int b = 31; b >= 0; --b) {
+      a.ws.counters[C_BSTART + b] = run;
+      run += a.ws.counters[C_BUCKET + b];
+      a.ws.counters[C_BFILL + b] = 0;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_order_scatter(RasterArgs a) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.T) return;
+  const int b = len_bucket(tile_len(a, t));
+  const uint32_t pos = a.ws.counters[C_BSTART + b] + atomicAdd(&a.ws.counters[C_BFILL + b], 1u);
+  a.ws.torder[pos] = t;
+}
+
+hipError_t launch_order(const RasterArgs& a, hipStream_t s) {
+  const uint32_t blocks = (a.T + 255) / 256;
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_order_hist, dim3(blocks), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(64), 0, s, a);
+  hipLaunchKernelGGL(k_order_scatter, dim3(blocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------- tile sort
+// One workgroup per tile.  Lists up to kSortCap keys are bitonic-sorted in
+// LDS; longer lists are sorted in kSortCap runs and merged pairwise (each key
+// finds its rank in the partner run by binary search) until one run remains.
+// Keys are unique for non-overlapping leaves, so the order is deterministic.
+constexpr int kSortThreads = 256;
+
+__device__ void lds_bitonic(unsigned long long* sk, uint32_t npow) {
+  for (uint32_t k = 2; k <= npow; k <<= 1) {
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      for (uint32_t i = threadIdx.x; i < (npow >> 1); i += kSortThreads) {
+        const uint32_t lo = ((i & ~(j - 1)) << 1) | (i & (j - 1));
+        const uint32_t hi = lo + j;
+        const bool asc = (lo & k) == 0;
+        const unsigned long long x = sk[lo], y = sk[hi];
+        if ((x > y) == asc) { sk[lo] = y; sk[hi] = x; }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+__device__ void sort_run(unsigned long long* sk, const unsigned long long* src,
+                         unsigned long long* dst, uint32_t n) {
+  uint32_t npow = 1;
+  while (npow < n) npow <<= 1;
+  for (uint32_t i = threadIdx.x; i < npow; i += kSortThreads) sk[i] = i < n ? src[i] : ~0ull;
+  __syncthreads();
+  lds_bitonic(sk, npow);
+  for (uint32_t i = threadIdx.x; i < n; i += kSortThreads) dst[i] = sk[i];
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_sort(RasterArgs a) {
+  __shared__ unsigned long long sk[kSortCap];
+  const uint32_t t = blockIdx.x;
+  const uint64_t s0 = a.ws.tstart[t] < a.cap ? a.ws.tstart[t] : a.cap;
+  const uint64_t s1 = a.ws.tstart[t + 1] < a.cap ? a.ws.tstart[t + 1] : a.cap;
+  const uint32_t n = uint32_t(s1 - s0);
+  if (n == 0) return;
+  unsigned long long* keys = a.ws.pairs + s0;
+  uint32_t* ids = a.ws.ids + s0;
+  if (n == 1) {
+    if (threadIdx.x == 0) ids[0] = uint32_t(keys[0] & kIdMask);
+    return;
+  }
+  if (n <= uint32_t(kSortCap)) {
+    uint32_t npow = 1;
+    while (npow < n) npow <<= 1;
+    for (uint32_t i = threadIdx.x; i < npow; i += kSortThreads) sk[i] = i < n ? keys[i] : ~0ull;
+    __syncthreads();
+    lds_bitonic(sk, npow);
+    for (uint32_t i = threadIdx.x; i < n; i += kSortThreads) ids[i] = uint32_t(sk[i] & kIdMask);
+    return;
+  }
+  // long list: sorted runs, then pairwise merges between keys and the temp
+  for (uint32_t r0 = 0; r0 < n; r0 += kSortCap) {
+    const uint32_t m = (n - r0) < uint32_t(kSortCap) ? (n - r0) : uint32_t(kSortCap);
+    sort_run(sk, keys + r0, keys + r0, m);
+  }
+  __threadfence_block();
+  __syncthreads();
+  unsigned long long* src = keys;
+  unsigned long long* dst = a.ws.mtmp + s0;
+  for (uint32_t r = kSortCap; r < n; r <<= 1) {
+    for (uint32_t i = threadIdx.x; i < n; i += kSortThreads) {
+      const uint32_t run = i / r;
+      const uint32_t rs = run * r;
+      const uint32_t prt = run ^ 1u;
+      const uint32_t ps = prt * r;
+      const unsigned long long key = src[i];
+      if (ps >= n) { dst[i] = key; continue; }
+      const uint32_t pe = (ps + r) < n ? (ps + r) : n;
+      // rank of key in the partner run: strict for the left run, non-strict
+      // for the right run (keys are unique; this keeps ties stable)
+      uint32_t lo = ps, hi = pe;
+      const bool left = (run & 1u) == 0;
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        const unsigned long long pk = src[mid];
+        const bool go_right = left ? (pk < key) : (pk <= key);
+        if (go_right) lo = mid + 1; else hi = mid;
+      }
+      const uint32_t ms = rs < ps ? rs : ps;
+      dst[ms + (i - rs) + (lo - ps)] = key;
+    }
+    __threadfence_block();
+    __syncthreads();
+    unsigned long long* tmp = src; src = dst; dst = tmp;
+  }
+  for (uint32_t i = threadIdx.x; i < n; i += kSortThreads) ids[i] = uint32_t(src[i] & kIdMask);
+}
+
+hipError_t launch_sort(const RasterArgs& a, hipStream_t s) {
+  if (a.T == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sort, dim3(a.T), dim3(kSortThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace lv

@@ -1,0 +1,499 @@
+// Per-tile compositing, forward (eq. 1-5) and backward (adjoint of eq. 2-4).
+//
+// Work unit: one TS x TS tile per workgroup, one pixel per lane, each wave an
+// 8 x 8 pixel block.  Workgroups are persistent and pop tiles from an atomic
+// queue ordered longest list first.  A tile's front-to-back voxel list is
+// staged in LDS `chunk` voxels at a time (geometry relative to the camera,
+// trilinear density coefficients, colour, pixel-centre coverage).  Per 64
+// staged voxels each wave builds, with 16 ballots, one 64-bit mask per pixel
+// row and per pixel column of its block; a lane's candidate set is the AND of
+// its row and column masks, so it visits only voxels whose projected box
+// covers its pixel centre, in list order (lowest bit first; backward: highest
+// first).  A lane stops once its transmittance falls below t_eps; the wave
+// and the workgroup stop when every lane has.
+//
+// Optical depth: the trilinear density along a chord is a cubic in t, so the
+// 2-point Gauss-Legendre rule on [t_in, t_out] integrates it exactly.
+//
+// w_max (eq. 5) is max-reduced per chunk in LDS (integer max on the bits of a
+// non-negative float, exact and order-independent) and then flushed with one
+// global atomic max per (tile, voxel).  Backward gradients (8 corner
+// densities + 3 colour channels per voxel) are pre-reduced per chunk in LDS
+// and flushed with one global atomic add per (tile, voxel, component).
+#include "lv_common.h"
+
+namespace lv {
+
+constexpr float kGL = 0.57735026918962576f;  // 1/sqrt(3): 2-point Gauss-Legendre node
+constexpr float kSmallTau = 0.03125f;
+
+template <int CH>
+struct Stage {
+  float rlo[3][CH];   // b - o
+  float rhi[3][CH];   // b + e - o
+  float su[3][CH];    // (b - o) / e
+  float inve[CH];
+  float cf[8][CH];    // trilinear density as a polynomial in (ux, uy, uz)
+  float col[3][CH];
+  uint32_t xr[CH];    // pixel-centre range x0 | x1 << 16
+  uint32_t yr[CH];
+  uint32_t id[CH];
+};
+
+struct Ray {
+  float d[3];
+  float inv[3];
+};
+
+__device__ __forceinline__ Ray pixel_ray(const lv_camera& c, int px, int py) {
+  const float dcx = (float(px) + 0.5f - c.cx) / c.fx;
+  const float dcy = (float(py) + 0.5f - c.cy) / c.fy;
+  float d0 = c.R[0] * dcx + c.R[3] * dcy + c.R[6];
+  float d1 = c.R[1] * dcx + c.R[4] * dcy + c.R[7];
+  float d2 = c.R[2] * dcx + c.R[5] * dcy + c.R[8];
+  const float in = 1.0f / sqrtf(d0 * d0 + d1 * d1 + d2 * d2);
+  Ray r;
+  r.d[0] = d0 * in; r.d[1] = d1 * in; r.d[2] = d2 * in;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    float x = r.d[a];
+    if (fabsf(x) < 1e-30f) x = x < 0.0f ? -1e-30f : 1e-30f;
+    r.inv[a] = 1.0f / x;
+  }
+  return r;
+}
+
+// Stage voxels [cb, cb + nc) of the tile list into LDS.
+template <int CH, int NT>
+__device__ __forceinline__ void stage_chunk(Stage<CH>& S, const RasterArgs& a, const uint32_t* ids,
+                                            uint32_t cb, uint32_t nc, int view,
+                                            const float o[3]) {
+  for (uint32_t k = threadIdx.x; k < uint32_t(CH); k += NT) {
+    if (k < nc) {
+      const uint32_t id = ids[cb + k];
+      const VoxRec vr = a.ws.vox[id];
+      const uint4 r0 = reinterpret_cast<const uint4*>(&a.ws.rec[size_t(view) * size_t(a.n) + id])[0];
+      const uint4 r1 = reinterpret_cast<const uint4*>(&a.ws.rec[size_t(view) * size_t(a.n) + id])[1];
+      const float e = vr.be.w;
+      const float ie = 1.0f / e;
+      const float bl[3] = {vr.be.x - o[0], vr.be.y - o[1], vr.be.z - o[2]};
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) {
+        S.rlo[ax][k] = bl[ax];
+        S.rhi[ax][k] = bl[ax] + e;
+        S.su[ax][k] = bl[ax] * ie;
+      }
+      S.inve[k] = ie;
+      const float s000 = vr.s0.x, s100 = vr.s0.y, s010 = vr.s0.z, s110 = vr.s0.w;
+      const float s001 = vr.s1.x, s101 = vr.s1.y, s011 = vr.s1.z, s111 = vr.s1.w;
+      S.cf[0][k] = s000;
+      S.cf[1][k] = s100 - s000;
+      S.cf[2][k] = s010 - s000;
+      S.cf[3][k] = s001 - s000;
+      S.cf[4][k] = (s110 - s100) - (s010 - s000);
+      S.cf[5][k] = (s101 - s100) - (s001 - s000);
+      S.cf[6][k] = (s011 - s010) - (s001 - s000);
+      S.cf[7][k] = ((s111 - s110) - (s101 - s100)) - ((s011 - s010) - (s001 - s000));
+      S.col[0][k] = __uint_as_float(r0.x);
+      S.col[1][k] = __uint_as_float(r0.y);
+      S.col[2][k] = __uint_as_float(r0.z);
+      S.xr[k] = r1.x;
+      S.yr[k] = r1.y;
+      S.id[k] = id;
+    } else {
+      S.xr[k] = 1u;   // empty range (x0 = 1 > x1 = 0)
+      S.yr[k] = 1u;
+      S.id[k] = 0u;
+    }
+  }
+}
+
+// bits r of an 8-bit row (or column) mask covered by [lo, hi] relative to org
+__device__ __forceinline__ uint32_t span_bits(uint32_t range, int org) {
+  const int lo = int(range & 0xFFFFu) - org;
+  const int hi = int(range >> 16) - org;
+  const int l = lo < 0 ? 0 : lo;
+  const int h = hi > 7 ? 7 : hi;
+  if (l > h) return 0u;
+  return ((2u << h) - 1u) & ~((1u << l) - 1u);
+}
+
+// candidate mask of this lane for voxels [64 w, 64 w + 64) of the chunk
+template <int CH>
+__device__ __forceinline__ unsigned long long lane_mask(const Stage<CH>& S, int w, int bx, int by,
+                                                        int lx, int ly) {
+  const int j = w * 64 + (threadIdx.x & 63);
+  const uint32_t rb = span_bits(S.yr[j], by);
+  const uint32_t cbits = span_bits(S.xr[j], bx);
+  unsigned long long myr = 0, myc = 0;
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const unsigned long long br = __ballot((rb >> r) & 1u);
+    const unsigned long long bc = __ballot((cbits >> r) & 1u);
+    myr = (ly == r) ? br : myr;
+    myc = (lx == r) ? bc : myc;
+  }
+  return myr & myc;
+}
+
+struct Seg {
+  bool hit;
+  float tn, tf;
+};
+
+template <int CH>
+__device__ __forceinline__ Seg slab(const Stage<CH>& S, int j, const Ray& ray) {
+  const float a0 = S.rlo[0][j] * ray.inv[0], b0 = S.rhi[0][j] * ray.inv[0];
+  const float a1 = S.rlo[1][j] * ray.inv[1], b1 = S.rhi[1][j] * ray.inv[1];
+  const float a2 = S.rlo[2][j] * ray.inv[2], b2 = S.rhi[2][j] * ray.inv[2];
+  Seg s;
+  s.tn = fmaxf(fmaxf(fminf(a0, b0), fminf(a1, b1)), fmaxf(fminf(a2, b2), 0.0f));
+  s.tf = fminf(fminf(fmaxf(a0, b0), fmaxf(a1, b1)), fmaxf(a2, b2));
+  s.hit = s.tf > s.tn;
+  return s;
+}
+
+struct Quad {
+  float tm, hl;
+  float ua[3], ub[3];
+  float tau;
+};
+
+template <int CH>
+__device__ __forceinline__ float trilin(const Stage<CH>& S, int j, const float u[3]) {
+  float t = fmaf(u[2], S.cf[7][j], S.cf[4][j]);
+  t = fmaf(u[1], t, S.cf[1][j]);
+  t = fmaf(u[2], S.cf[5][j], t);
+  const float q = fmaf(u[2], S.cf[6][j], S.cf[2][j]);
+  float s = fmaf(u[0], t, S.cf[0][j]);
+  s = fmaf(u[1], q, s);
+  s = fmaf(u[2], S.cf[3][j], s);
+  return s;
+}
+
+template <int CH>
+__device__ __forceinline__ Quad quad(const Stage<CH>& S, int j, const Ray& ray, const Seg& sg) {
+  Quad q;
+  q.tm = 0.5f * (sg.tn + sg.tf);
+  q.hl = 0.5f * (sg.tf - sg.tn);
+  const float ta = fmaf(-q.hl, kGL, q.tm), tb = fmaf(q.hl, kGL, q.tm);
+  const float ie = S.inve[j];
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    const float du = ray.d[ax] * ie;
+    q.ua[ax] = fmaf(ta, du, -S.su[ax][j]);
+    q.ub[ax] = fmaf(tb, du, -S.su[ax][j]);
+  }
+  const float sa = trilin(S, j, q.ua), sb = trilin(S, j, q.ub);
+  q.tau = fmaxf(q.hl * (sa + sb), 0.0f);
+  return q;
+}
+
+// alpha = 1 - exp(-tau) without cancellation for small tau
+__device__ __forceinline__ float opacity(float tau, float ex) {
+  if (tau < kSmallTau) {
+    return tau * (1.0f - tau * (0.5f - tau * (0.16666667f - tau * 0.041666667f)));
+  }
+  return 1.0f - ex;
+}
+
+// ======================================================================
+// forward
+template <int TS, int NW>
+__global__ __launch_bounds__(TS* TS) void k_composite_fwd(RasterArgs a) {
+  constexpr int NT = TS * TS;
+  constexpr int CH = 64 * NW;
+  constexpr int BPR = TS / 8;
+  __shared__ Stage<CH> S;
+  __shared__ uint32_t s_wmax[CH];
+  __shared__ uint32_t s_tile;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lx = lane & 7, ly = lane >> 3;
+  const int wbx = (wave % BPR) * 8, wby = (wave / BPR) * 8;
+
+  for (;;) {
+    if (threadIdx.x == 0) s_tile = atomicAdd(&a.ws.counters[C_QFWD], 1u);
+    __syncthreads();
+    const uint32_t qi = s_tile;
+    __syncthreads();
+    if (qi >= a.T) break;
+    const uint32_t gt = a.ws.torder[qi];
+    const int v = view_of_tile(a.ws.views, a.V, gt);
+    const ViewTab vt = a.ws.views[v];
+    const uint32_t lt = gt - vt.tile_base;
+    const int tx = int(lt % vt.tiles_x), ty = int(lt / vt.tiles_x);
+    const int bx = tx * TS + wbx, by = ty * TS + wby;   // wave block origin (pixels)
+    const int px = bx + lx, py = by + ly;
+    const bool inimg = px < vt.W && py < vt.H;
+    const lv_camera& cam = a.cams[v];
+    const float o[3] = {cam.o[0], cam.o[1], cam.o[2]};
+    const Ray ray = pixel_ray(cam, px, py);
+    const uint64_t s0 = a.ws.tstart[gt] < a.cap ? a.ws.tstart[gt] : a.cap;
+    const uint64_t s1 = a.ws.tstart[gt + 1] < a.cap ? a.ws.tstart[gt + 1] : a.cap;
+    const uint32_t count = uint32_t(s1 - s0);
+    const uint32_t* ids = a.ws.ids + s0;
+
+    float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, D = 0.0f, Tpre = 1.0f;
+    uint32_t nlast = 0;
+    bool done = !inimg;
+    for (uint32_t cb = 0; cb < count; cb += CH) {
+      const uint32_t nc = (count - cb) < uint32_t(CH) ? (count - cb) : uint32_t(CH);
+      stage_chunk<CH, NT>(S, a, ids, cb, nc, v, o);
+      for (int k = threadIdx.x; k < CH; k += NT) s_wmax[k] = 0u;
+      __syncthreads();
+#pragma unroll 1
+      for (int w = 0; w < NW; ++w) {
+        if (uint32_t(w * 64) >= nc) break;
+        unsigned long long m = lane_mask(S, w, bx, by, lx, ly);
+        if (done) m = 0;
+        while (m) {
+          const int jj = w * 64 + __builtin_ctzll(m);
+          m &= m - 1;
+          const Seg sg = slab(S, jj, ray);
+          if (!sg.hit) continue;
+          const Quad q = quad(S, jj, ray, sg);
+          const float ex = __expf(-q.tau);
+          const float al = opacity(q.tau, ex);
+          const float wk = T * al;
+          C0 = fmaf(wk, S.col[0][jj], C0);
+          C1 = fmaf(wk, S.col[1][jj], C1);
+          C2 = fmaf(wk, S.col[2][jj], C2);
+          D = fmaf(wk, q.tm, D);
+          atomicMax(&s_wmax[jj], __float_as_uint(wk));
+          Tpre = T;
+          nlast = cb + uint32_t(jj) + 1u;
+          T = T * ex;
+          if (T < a.t_eps) { done = true; m = 0; }
+        }
+      }
+      __syncthreads();
+      for (uint32_t k = threadIdx.x; k < nc; k += NT) {
+        const uint32_t u = s_wmax[k];
+        if (u) atomicMax(reinterpret_cast<unsigned int*>(a.wmax) + S.id[k], u);
+      }
+      if (__syncthreads_and(done ? 1 : 0)) break;
+    }
+    if (inimg) {
+      const uint64_t local = uint64_t(py) * uint64_t(vt.W) + uint64_t(px);
+      const uint64_t npv = uint64_t(vt.W) * uint64_t(vt.H);
+      const uint64_t g = vt.pix_base + local;
+      float* rgb = a.rgb + 3 * vt.pix_base + local;
+      rgb[0] = fmaf(T, a.bg[0], C0);
+      rgb[npv] = fmaf(T, a.bg[1], C1);
+      rgb[2 * npv] = fmaf(T, a.bg[2], C2);
+      a.depth[g] = D;
+      a.alpha[g] = 1.0f - T;
+      a.ws.nlast[g] = nlast;
+      a.ws.tpre[g] = Tpre;
+    }
+  }
+}
+
+// ======================================================================
+// backward: back-to-front adjoint sweep.  With T_k the transmittance after
+// hit k and S_k^C = sum_{j>k} w_j c_j (likewise S^D for depth):
+//   dL/dtau_k = g_C . (T_k c_k - S_k^C - T_K bg) + g_D (T_k tm_k - S_k^D) + g_A T_K
+//   dL/dsigma_corner += dL/dtau_k * integral of the corner's trilinear weight
+//   dL/dcolour_k     += w_k g_C
+// T_{k-1} = T_k exp(tau_k), starting from the transmittance saved before the
+// last hit, so no per-sample state is stored.
+template <int TS, int NW>
+__global__ __launch_bounds__(TS* TS) void k_composite_bwd(RasterArgs a) {
+  constexpr int NT = TS * TS;
+  constexpr int CH = 64 * NW;
+  constexpr int BPR = TS / 8;
+  __shared__ Stage<CH> S;
+  __shared__ float s_g[11][CH];
+  __shared__ uint32_t s_tile, s_maxn;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lx = lane & 7, ly = lane >> 3;
+  const int wbx = (wave % BPR) * 8, wby = (wave / BPR) * 8;
+
+  for (;;) {
+    if (threadIdx.x == 0) {
+      s_tile = atomicAdd(&a.ws.counters[C_QBWD], 1u);
+      s_maxn = 0u;
+    }
+    __syncthreads();
+    const uint32_t qi = s_tile;
+    if (qi >= a.T) break;
+    const uint32_t gt = a.ws.torder[qi];
+    const int v = view_of_tile(a.ws.views, a.V, gt);
+    const ViewTab vt = a.ws.views[v];
+    const uint32_t lt = gt - vt.tile_base;
+    const int tx = int(lt % vt.tiles_x), ty = int(lt / vt.tiles_x);
+    const int bx = tx * TS + wbx, by = ty * TS + wby;
+    const int px = bx + lx, py = by + ly;
+    const bool inimg = px < vt.W && py < vt.H;
+    const lv_camera& cam = a.cams[v];
+    const float o[3] = {cam.o[0], cam.o[1], cam.o[2]};
+    const Ray ray = pixel_ray(cam, px, py);
+    const uint64_t s0 = a.ws.tstart[gt] < a.cap ? a.ws.tstart[gt] : a.cap;
+    const uint32_t* ids = a.ws.ids + s0;
+
+    uint32_t nlast = 0;
+    float Tb = 1.0f, gC0 = 0.0f, gC1 = 0.0f, gC2 = 0.0f, gD = 0.0f, gA = 0.0f;
+    if (inimg) {
+      const uint64_t local = uint64_t(py) * uint64_t(vt.W) + uint64_t(px);
+      const uint64_t npv = uint64_t(vt.W) * uint64_t(vt.H);
+      const uint64_t g = vt.pix_base + local;
+      nlast = a.ws.nlast[g];
+      Tb = a.ws.tpre[g];
+      const float* dr = a.d_rgb + 3 * vt.pix_base + local;
+      gC0 = dr[0]; gC1 = dr[npv]; gC2 = dr[2 * npv];
+      gD = a.d_depth ? a.d_depth[g] : 0.0f;
+      gA = a.d_alpha ? a.d_alpha[g] : 0.0f;
+    }
+    if (nlast) atomicMax(&s_maxn, nlast);
+    __syncthreads();
+    const uint32_t maxn = s_maxn;
+    __syncthreads();
+
+    bool first = true;
+    float base = 0.0f, SC0 = 0.0f, SC1 = 0.0f, SC2 = 0.0f, SD = 0.0f;
+    const int nch = int((maxn + CH - 1) / CH);
+    for (int ci = nch - 1; ci >= 0; --ci) {
+      const uint32_t cb = uint32_t(ci) * CH;
+      const uint32_t nc = (maxn - cb) < uint32_t(CH) ? (maxn - cb) : uint32_t(CH);
+      stage_chunk<CH, NT>(S, a, ids, cb, nc, v, o);
+      for (int k = threadIdx.x; k < CH; k += NT)
+#pragma unroll
+        for (int c = 0; c < 11; ++c) s_g[c][k] = 0.0f;
+      __syncthreads();
+#pragma unroll 1
+      for (int w = NW - 1; w >= 0; --w) {
+        if (uint32_t(w * 64) >= nc) continue;
+        unsigned long long m = lane_mask(S, w, bx, by, lx, ly);
+        const int lim = int(nlast) - int(cb) - w * 64;
+        if (lim <= 0) m = 0;
+        else if (lim < 64) m &= (1ull << lim) - 1ull;
+        while (m) {
+          const int jb = 63 - __builtin_clzll(m);
+          m &= ~(1ull << jb);
+          const int jj = w * 64 + jb;
+          const Seg sg = slab(S, jj, ray);
+          if (!sg.hit) continue;
+          const Quad q = quad(S, jj, ray, sg);
+          const float ex = __expf(-q.tau);
+          const float al = opacity(q.tau, ex);
+          float Tafter, Tbefore;
+          if (first) {
+            Tbefore = Tb;
+            Tafter = Tb * ex;
+            base = Tafter * (gA - (gC0 * a.bg[0] + gC1 * a.bg[1] + gC2 * a.bg[2]));
+            first = false;
+          } else {
+            Tafter = Tb;
+            Tbefore = Tb * __expf(q.tau);
+          }
+          const float wk = Tbefore * al;
+          const float c0 = S.col[0][jj], c1 = S.col[1][jj], c2 = S.col[2][jj];
+          float dtau = base + gD * (Tafter * q.tm - SD);
+          dtau = fmaf(gC0, Tafter * c0 - SC0, dtau);
+          dtau = fmaf(gC1, Tafter * c1 - SC1, dtau);
+          dtau = fmaf(gC2, Tafter * c2 - SC2, dtau);
+          const float gh = dtau * q.hl;
+          // corner weights at both Gauss points
+          float wa[8], wb[8];
+          {
+            const float x1 = q.ua[0], y1 = q.ua[1], z1 = q.ua[2];
+            const float x0 = 1.0f - x1, y0 = 1.0f - y1, z0 = 1.0f - z1;
+            const float y0z0 = y0 * z0, y1z0 = y1 * z0, y0z1 = y0 * z1, y1z1 = y1 * z1;
+            wa[0] = x0 * y0z0; wa[1] = x1 * y0z0; wa[2] = x0 * y1z0; wa[3] = x1 * y1z0;
+            wa[4] = x0 * y0z1; wa[5] = x1 * y0z1; wa[6] = x0 * y1z1; wa[7] = x1 * y1z1;
+          }
+          {
+            const float x1 = q.ub[0], y1 = q.ub[1], z1 = q.ub[2];
+            const float x0 = 1.0f - x1, y0 = 1.0f - y1, z0 = 1.0f - z1;
+            const float y0z0 = y0 * z0, y1z0 = y1 * z0, y0z1 = y0 * z1, y1z1 = y1 * z1;
+            wb[0] = x0 * y0z0; wb[1] = x1 * y0z0; wb[2] = x0 * y1z0; wb[3] = x1 * y1z0;
+            wb[4] = x0 * y0z1; wb[5] = x1 * y0z1; wb[6] = x0 * y1z1; wb[7] = x1 * y1z1;
+          }
+#pragma unroll
+          for (int c = 0; c < 8; ++c) atomicAdd(&s_g[c][jj], gh * (wa[c] + wb[c]));
+          atomicAdd(&s_g[8][jj], wk * gC0);
+          atomicAdd(&s_g[9][jj], wk * gC1);
+          atomicAdd(&s_g[10][jj], wk * gC2);
+          SC0 = fmaf(wk, c0, SC0);
+          SC1 = fmaf(wk, c1, SC1);
+          SC2 = fmaf(wk, c2, SC2);
+          SD = fmaf(wk, q.tm, SD);
+          Tb = Tbefore;
+        }
+      }
+      __syncthreads();
+      for (uint32_t k = threadIdx.x; k < nc; k += NT) {
+        const uint32_t id = S.id[k];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          const float g = s_g[c][k];
+          if (g != 0.0f) unsafeAtomicAdd(&a.d_density[size_t(c) * size_t(a.n) + id], g);
+        }
+        float* dc = a.ws.dcol + (size_t(v) * size_t(a.n) + id) * 3;
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+          const float g = s_g[8 + ch][k];
+          if (g != 0.0f) unsafeAtomicAdd(&dc[ch], g);
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// ------------------------------------------------------------- launchers
+template <typename K>
+static int persistent_grid(K kernel, int nt, uint32_t T, int grid_cap) {
+  int dev = 0, cus = 256, per = 1;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  }
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, nt, 0) != hipSuccess || per < 1) per = 1;
+  long g = long(cus) * per;
+  if (grid_cap > 0 && g > grid_cap) g = grid_cap;
+  if (g > long(T)) g = long(T);
+  if (g < 1) g = 1;
+  return int(g);
+}
+
+template <int TS, int NW>
+static hipError_t fwd_inst(const RasterArgs& a, int grid_cap, hipStream_t s) {
+  auto k = k_composite_fwd<TS, NW>;
+  const int g = persistent_grid(k, TS * TS, a.T, grid_cap);
+  hipLaunchKernelGGL(k, dim3(g), dim3(TS * TS), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int TS, int NW>
+static hipError_t bwd_inst(const RasterArgs& a, int grid_cap, hipStream_t s) {
+  auto k = k_composite_bwd<TS, NW>;
+  const int g = persistent_grid(k, TS * TS, a.T, grid_cap);
+  hipLaunchKernelGGL(k, dim3(g), dim3(TS * TS), 0, s, a);
+  return hipGetLastError();
+}
+
+#define LV_DISPATCH(FN, a, chunk, cap, s)                              \
+  switch (a.TS * 1000 + chunk) {                                       \
+    case 8064: return FN<8, 1>(a, cap, s);                             \
+    case 8128: return FN<8, 2>(a, cap, s);                             \
+    case 8256: return FN<8, 4>(a, cap, s);                             \
+    case 16064: return FN<16, 1>(a, cap, s);                           \
+    case 16128: return FN<16, 2>(a, cap, s);                           \
+    case 16256: return FN<16, 4>(a, cap, s);                           \
+    case 32064: return FN<32, 1>(a, cap, s);                           \
+    case 32128: return FN<32, 2>(a, cap, s);                           \
+    case 32256: return FN<32, 4>(a, cap, s);                           \
+    default: return hipErrorInvalidValue;                              \
+  }
+
+hipError_t launch_composite_fwd(const RasterArgs& a, int chunk, int grid_cap, hipStream_t s) {
+  if (a.T == 0) return hipSuccess;
+  LV_DISPATCH(fwd_inst, a, chunk, grid_cap, s);
+}
+
+hipError_t launch_composite_bwd(const RasterArgs& a, int chunk, int grid_cap, hipStream_t s) {
+  if (a.T == 0) return hipSuccess;
+  LV_DISPATCH(bwd_inst, a, chunk, grid_cap, s);
+}
+
+}  // namespace lv

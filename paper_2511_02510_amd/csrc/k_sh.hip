@@ -1,0 +1,69 @@
+// Backward tail: colour gradients of every (view, voxel) record are taken
+// through the clamp at zero and the SH expansion to the SH coefficients,
+// summed over views.  One thread per voxel; the output rows are written
+// coalesced ([3 (deg+1)^2][n]) and fully overwritten.
+#include "lv_common.h"
+
+namespace lv {
+
+hipError_t launch_bwd_setup(const RasterArgs& a, hipStream_t s) {
+  hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(a.d_density), 8ull * uint64_t(a.n), 0u, s);
+  if (e != hipSuccess) return e;
+  e = launch_fill_u32(reinterpret_cast<uint32_t*>(a.ws.dcol), 3ull * uint64_t(a.n) * uint64_t(a.V), 0u, s);
+  if (e != hipSuccess) return e;
+  return launch_fill_u32(a.ws.counters + C_QBWD, 1, 0u, s);
+}
+
+template <int DEG>
+__global__ __launch_bounds__(256) void k_sh_bwd(RasterArgs a) {
+  constexpr int NB = (DEG + 1) * (DEG + 1);
+  const int64_t n = a.n;
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float acc[NB][3];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) acc[j][0] = acc[j][1] = acc[j][2] = 0.0f;
+  const VoxRec vr = a.ws.vox[i];
+  const float he = 0.5f * vr.be.w;
+  const float xv0 = vr.be.x + he, xv1 = vr.be.y + he, xv2 = vr.be.z + he;
+  for (int v = 0; v < a.V; ++v) {
+    const size_t r = size_t(v) * size_t(n) + size_t(i);
+    const uint32_t flags = a.ws.rec[r].flags;
+    if (!(flags & 8u)) continue;
+    const float* dcp = a.ws.dcol + 3 * r;
+    const float g0 = (flags & 1u) ? dcp[0] : 0.0f;
+    const float g1 = (flags & 2u) ? dcp[1] : 0.0f;
+    const float g2 = (flags & 4u) ? dcp[2] : 0.0f;
+    if (g0 == 0.0f && g1 == 0.0f && g2 == 0.0f) continue;
+    const lv_camera& cam = a.cams[v];
+    float dx = xv0 - cam.o[0], dy = xv1 - cam.o[1], dz = xv2 - cam.o[2];
+    const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+    dx *= inv; dy *= inv; dz *= inv;
+    float Y[16];
+    sh_basis<DEG>(dx, dy, dz, Y);
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      acc[j][0] = fmaf(Y[j], g0, acc[j][0]);
+      acc[j][1] = fmaf(Y[j], g1, acc[j][1]);
+      acc[j][2] = fmaf(Y[j], g2, acc[j][2]);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < NB; ++j)
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) a.d_sh[size_t(j * 3 + ch) * size_t(n) + size_t(i)] = acc[j][ch];
+}
+
+hipError_t launch_sh_bwd(const RasterArgs& a, hipStream_t s) {
+  const uint32_t blocks = uint32_t((a.n + 255) / 256);
+  if (blocks == 0) return hipSuccess;
+  switch (a.deg) {
+    case 0: hipLaunchKernelGGL(k_sh_bwd<0>, dim3(blocks), dim3(256), 0, s, a); break;
+    case 1: hipLaunchKernelGGL(k_sh_bwd<1>, dim3(blocks), dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL(k_sh_bwd<2>, dim3(blocks), dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL(k_sh_bwd<3>, dim3(blocks), dim3(256), 0, s, a); break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace lv

@@ -1,0 +1,612 @@
+// Host side of the C-ABI: argument validation, workspace planning, kernel
+// orchestration on the caller's stream, graph capture, per-phase timing and
+// the tile/chunk autotuner.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lv_common.h"
+
+namespace lv {
+uint64_t loss_ws_bytes(int V);
+uint64_t quant_ws_bytes(int64_t n, int B);
+hipError_t run_lf_weight(const lv_camera* cams_dev, int V, uint64_t max_pix, const float* target,
+                         float gamma, int form, float eps, float* weight, void* ws, hipStream_t s);
+hipError_t run_l1_grad(const lv_camera* cams_dev, int V, uint64_t max_pix, const float* rgb,
+                       const float* target, const float* weight, float* loss, float* d_rgb,
+                       hipStream_t s);
+hipError_t run_depth_quantile(const RasterArgs& a, int B, double q, void* ws, float* tau,
+                              uint8_t* prune, uint8_t* out_bins, hipStream_t s);
+}  // namespace lv
+
+struct lv_context {
+  int device = 0;
+  std::string err;
+  bool timing = false;
+  bool capturing = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  struct Pending {
+    int phase;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+  double ms[LV_PH_COUNT] = {};
+  int64_t calls[LV_PH_COUNT] = {};
+
+  hipEvent_t event() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+};
+
+namespace {
+
+lv_status fail(lv_context* ctx, lv_status s, const char* fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    ctx->err = buf;
+  }
+  return s;
+}
+
+lv_status hip_fail(lv_context* ctx, hipError_t e, const char* where) {
+  return fail(ctx, LV_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+struct PhaseTimer {
+  lv_context* c;
+  int ph;
+  hipStream_t s;
+  hipEvent_t a = nullptr, b = nullptr;
+  PhaseTimer(lv_context* ctx, int phase, hipStream_t st) : c(ctx), ph(phase), s(st) {
+    if (c && c->timing && !c->capturing) {
+      a = c->event();
+      b = c->event();
+      if (a && b) hipEventRecord(a, s);
+      else a = b = nullptr;
+    }
+  }
+  ~PhaseTimer() {
+    if (a) {
+      hipEventRecord(b, s);
+      c->pending.push_back({ph, a, b});
+    }
+  }
+};
+
+bool finite_pos(float x) { return std::isfinite(x) && x > 0.0f; }
+
+lv_status check_frame(lv_context* ctx, const lv_frame* fr) {
+  if (!fr) return fail(ctx, LV_ERR_ARG, "frame is NULL");
+  if (fr->n_views < 1 || fr->n_views > LV_MAX_VIEWS)
+    return fail(ctx, LV_ERR_ARG, "n_views=%d outside [1, %d]", fr->n_views, LV_MAX_VIEWS);
+  if (!fr->cams_host || !fr->cams_dev) return fail(ctx, LV_ERR_ARG, "camera arrays must be non-NULL");
+  for (int v = 0; v < fr->n_views; ++v) {
+    const lv_camera& c = fr->cams_host[v];
+    if (c.width < 1 || c.height < 1 || c.width > 32767 || c.height > 32767)
+      return fail(ctx, LV_ERR_ARG, "view %d: size %dx%d outside [1, 32767]", v, c.width, c.height);
+    if (!finite_pos(c.fx) || !finite_pos(c.fy) || !std::isfinite(c.cx) || !std::isfinite(c.cy))
+      return fail(ctx, LV_ERR_ARG, "view %d: invalid intrinsics", v);
+    for (int k = 0; k < 9; ++k)
+      if (!std::isfinite(c.R[k])) return fail(ctx, LV_ERR_ARG, "view %d: non-finite R", v);
+    for (int k = 0; k < 3; ++k)
+      if (!std::isfinite(c.o[k])) return fail(ctx, LV_ERR_ARG, "view %d: non-finite centre", v);
+  }
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(fr->bg[k])) return fail(ctx, LV_ERR_ARG, "non-finite background");
+  return LV_OK;
+}
+
+lv_status check_voxels(lv_context* ctx, const lv_voxels* vx, bool need_params) {
+  if (!vx) return fail(ctx, LV_ERR_ARG, "voxels is NULL");
+  if (vx->n < 0 || vx->n >= (int64_t(1) << lv::kIdBits))
+    return fail(ctx, LV_ERR_ARG, "n=%lld outside [0, 2^28)", (long long)vx->n);
+  if (vx->sh_degree < 0 || vx->sh_degree > 3)
+    return fail(ctx, LV_ERR_ARG, "sh_degree=%d outside [0, 3]", vx->sh_degree);
+  if (!finite_pos(vx->root_size)) return fail(ctx, LV_ERR_ARG, "root_size must be finite and > 0");
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(vx->root_min[k])) return fail(ctx, LV_ERR_ARG, "non-finite root_min");
+  if (vx->n > 0) {
+    if (!vx->ijk || !vx->level) return fail(ctx, LV_ERR_ARG, "ijk/level must be non-NULL");
+    if (need_params && (!vx->density || !vx->sh))
+      return fail(ctx, LV_ERR_ARG, "density/sh must be non-NULL");
+  }
+  return LV_OK;
+}
+
+lv_status check_settings(lv_context* ctx, const lv_settings* st) {
+  if (!st) return fail(ctx, LV_ERR_ARG, "settings is NULL");
+  if (st->tile != 8 && st->tile != 16 && st->tile != 32)
+    return fail(ctx, LV_ERR_ARG, "tile=%d not in {8, 16, 32}", st->tile);
+  if (st->chunk != 64 && st->chunk != 128 && st->chunk != 256)
+    return fail(ctx, LV_ERR_ARG, "chunk=%d not in {64, 128, 256}", st->chunk);
+  if (!(st->t_eps > 0.0f) || !(st->t_eps <= 1e-5f))
+    return fail(ctx, LV_ERR_ARG, "t_eps=%g outside (0, 1e-5]", double(st->t_eps));
+  if (st->pair_capacity >= (uint64_t(1) << 32))
+    return fail(ctx, LV_ERR_ARG, "pair_capacity must be < 2^32");
+  return LV_OK;
+}
+
+lv_status validate_all(lv_context* ctx, const lv_voxels* vx, const lv_frame* fr,
+                       const lv_settings* st, lv::Layout* L) {
+  lv_status s = check_voxels(ctx, vx, true);
+  if (s != LV_OK) return s;
+  if ((s = check_frame(ctx, fr)) != LV_OK) return s;
+  if ((s = check_settings(ctx, st)) != LV_OK) return s;
+  lv::Layout tmp;
+  if (!lv::make_layout(vx, fr, st, L ? *L : tmp))
+    return fail(ctx, LV_ERR_ARG, "too many tiles for these views and tile size");
+  return LV_OK;
+}
+
+lv::RasterArgs make_args(const lv::Layout& L, void* ws, const lv_voxels* vx, const lv_frame* fr,
+                         const lv_settings* st) {
+  lv::RasterArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.ws = lv::bind(L, ws);
+  a.n = vx->n;
+  a.deg = vx->sh_degree;
+  for (int k = 0; k < 3; ++k) a.root_min[k] = vx->root_min[k];
+  a.root_size = vx->root_size;
+  a.ijk = vx->ijk;
+  a.level = vx->level;
+  a.density = vx->density;
+  a.sh = vx->sh;
+  a.V = fr->n_views;
+  a.cams = fr->cams_dev;
+  for (int k = 0; k < 3; ++k) a.bg[k] = fr->bg[k];
+  a.TS = L.TS;
+  a.T = L.T;
+  a.P = L.P;
+  a.cap = L.cap;
+  a.t_eps = st ? st->t_eps : 1e-6f;
+  return a;
+}
+
+#define LV_TRY(expr, where)                          \
+  do {                                               \
+    hipError_t _e = (expr);                          \
+    if (_e != hipSuccess) return hip_fail(ctx, _e, where); \
+  } while (0)
+
+}  // namespace
+
+extern "C" {
+
+const char* lv_status_str(lv_status s) {
+  switch (s) {
+    case LV_OK: return "ok";
+    case LV_ERR_ARG: return "invalid argument";
+    case LV_ERR_HIP: return "HIP runtime error";
+    case LV_ERR_CAPACITY: return "pair capacity exceeded";
+    case LV_ERR_UNSUPPORTED: return "unsupported";
+    case LV_ERR_STATE: return "invalid call order";
+  }
+  return "unknown status";
+}
+
+const char* lv_last_error(const lv_context* ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+void lv_default_settings(lv_settings* s) {
+  if (!s) return;
+  s->tile = 16;
+  s->chunk = 64;
+  s->t_eps = 1e-6f;
+  s->pair_capacity = 0;
+}
+
+lv_status lv_create(lv_context** out, int hip_device) {
+  if (!out) return LV_ERR_ARG;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count < 1) return LV_ERR_HIP;
+  if (hip_device < 0 || hip_device >= count) return LV_ERR_ARG;
+  if (hipSetDevice(hip_device) != hipSuccess) return LV_ERR_HIP;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess) return LV_ERR_HIP;
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return LV_ERR_UNSUPPORTED;
+  lv_context* c = new lv_context();
+  c->device = hip_device;
+  *out = c;
+  return LV_OK;
+}
+
+void lv_destroy(lv_context* ctx) {
+  if (!ctx) return;
+  if (ctx->exec) hipGraphExecDestroy(ctx->exec);
+  if (ctx->graph) hipGraphDestroy(ctx->graph);
+  for (auto& p : ctx->pending) { hipEventDestroy(p.a); hipEventDestroy(p.b); }
+  for (auto e : ctx->pool) hipEventDestroy(e);
+  delete ctx;
+}
+
+lv_status lv_validate(const lv_voxels* vox, const lv_frame* frame, const lv_settings* st) {
+  return validate_all(nullptr, vox, frame, st, nullptr);
+}
+
+lv_status lv_query_sizes(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
+                         const lv_settings* st, uint64_t* workspace_bytes) {
+  if (!workspace_bytes) return fail(ctx, LV_ERR_ARG, "workspace_bytes is NULL");
+  lv::Layout L;
+  lv_status s = validate_all(ctx, vox, frame, st, &L);
+  if (s != LV_OK) return s;
+  *workspace_bytes = L.total;
+  return LV_OK;
+}
+
+lv_status lv_forward(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
+                     const lv_settings* st, void* workspace, float* rgb, float* depth,
+                     float* alpha, float* wmax, hipStream_t stream) {
+  if (!ctx) return LV_ERR_ARG;
+  lv::Layout L;
+  lv_status s = validate_all(ctx, vox, frame, st, &L);
+  if (s != LV_OK) return s;
+  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255))
+    return fail(ctx, LV_ERR_ARG, "workspace must be non-NULL and 256-byte aligned");
+  if (!rgb || !depth || !alpha) return fail(ctx, LV_ERR_ARG, "rgb/depth/alpha must be non-NULL");
+  if (vox->n > 0 && !wmax) return fail(ctx, LV_ERR_ARG, "wmax must be non-NULL");
+  lv::RasterArgs a = make_args(L, workspace, vox, frame, st);
+  a.rgb = rgb;
+  a.depth = depth;
+  a.alpha = alpha;
+  a.wmax = wmax;
+  {
+    PhaseTimer t(ctx, LV_PH_SETUP, stream);
+    LV_TRY(lv::launch_setup(a, stream), "setup");
+    LV_TRY(lv::launch_fill_u32(a.ws.tcount, uint64_t(L.T) + 1, 0u, stream), "fill tile counts");
+  }
+  {
+    PhaseTimer t(ctx, LV_PH_PREPROCESS, stream);
+    LV_TRY(lv::launch_preprocess(a, stream), "preprocess");
+  }
+  {
+    PhaseTimer t(ctx, LV_PH_SCAN, stream);
+    LV_TRY(lv::launch_scan_tiles(a, L.nblk_scan, stream), "scan");
+  }
+  {
+    PhaseTimer t(ctx, LV_PH_EMIT, stream);
+    LV_TRY(lv::launch_emit(a, stream), "emit");
+  }
+  {
+    PhaseTimer t(ctx, LV_PH_SORT, stream);
+    LV_TRY(lv::launch_sort(a, stream), "sort");
+  }
+  {
+    PhaseTimer t(ctx, LV_PH_ORDER, stream);
+    LV_TRY(lv::launch_order(a, stream), "order");
+  }
+  {
+    PhaseTimer t(ctx, LV_PH_COMPOSITE_FWD, stream);
+    LV_TRY(lv::launch_composite_fwd(a, st->chunk, 0, stream), "composite forward");
+  }
+  return LV_OK;
+}
+
+lv_status lv_backward(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
+                      const lv_settings* st, void* workspace, const float* d_rgb,
+                      const float* d_depth, const float* d_alpha, float* d_density, float* d_sh,
+                      hipStream_t stream) {
+  if (!ctx) return LV_ERR_ARG;
+  lv::Layout L;
+  lv_status s = validate_all(ctx, vox, frame, st, &L);
+  if (s != LV_OK) return s;
+  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255))
+    return fail(ctx, LV_ERR_ARG, "workspace must be non-NULL and 256-byte aligned");
+  if (!d_rgb) return fail(ctx, LV_ERR_ARG, "d_rgb must be non-NULL");
+  if (vox->n > 0 && (!d_density || !d_sh))
+    return fail(ctx, LV_ERR_ARG, "d_density/d_sh must be non-NULL");
+  lv::RasterArgs a = make_args(L, workspace, vox, frame, st);
+  a.d_rgb = d_rgb;
+  a.d_depth = d_depth;
+  a.d_alpha = d_alpha;
+  a.d_density = d_density;
+  a.d_sh = d_sh;
+  {
+    PhaseTimer t(ctx, LV_PH_BWD_SETUP, stream);
+    LV_TRY(lv::launch_bwd_setup(a, stream), "backward setup");
+  }
+  {
+    PhaseTimer t(ctx, LV_PH_COMPOSITE_BWD, stream);
+    LV_TRY(lv::launch_composite_bwd(a, st->chunk, 0, stream), "composite backward");
+  }
+  {
+    PhaseTimer t(ctx, LV_PH_SH_BWD, stream);
+    LV_TRY(lv::launch_sh_bwd(a, stream), "sh backward");
+  }
+  return LV_OK;
+}
+
+lv_status lv_check_overflow(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
+                            const lv_settings* st, const void* workspace, uint64_t* pairs_needed,
+                            hipStream_t stream) {
+  if (!ctx) return LV_ERR_ARG;
+  lv::Layout L;
+  lv_status s = validate_all(ctx, vox, frame, st, &L);
+  if (s != LV_OK) return s;
+  if (!workspace) return fail(ctx, LV_ERR_ARG, "workspace is NULL");
+  LV_TRY(hipStreamSynchronize(stream), "synchronize");
+  uint32_t c[2] = {0, 0};
+  const char* base = static_cast<const char*>(workspace) + L.off_counters;
+  LV_TRY(hipMemcpy(c, base, sizeof(c), hipMemcpyDeviceToHost), "read counters");
+  if (pairs_needed) *pairs_needed = c[lv::C_PAIRS];
+  if (c[lv::C_OVERFLOW]) {
+    return fail(ctx, LV_ERR_CAPACITY, "%u (tile, voxel) pairs needed, capacity %llu",
+                c[lv::C_PAIRS], (unsigned long long)L.cap);
+  }
+  return LV_OK;
+}
+
+lv_status lv_export_bins(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
+                         const lv_settings* st, const void* workspace, uint32_t* tile_start,
+                         uint32_t* ids, uint64_t* codes, int32_t* rects, uint8_t* vis,
+                         hipStream_t stream) {
+  if (!ctx) return LV_ERR_ARG;
+  lv::Layout L;
+  lv_status s = validate_all(ctx, vox, frame, st, &L);
+  if (s != LV_OK) return s;
+  if (!workspace) return fail(ctx, LV_ERR_ARG, "workspace is NULL");
+  LV_TRY(hipStreamSynchronize(stream), "synchronize");
+  const char* base = static_cast<const char*>(workspace);
+  std::vector<uint32_t> ts(size_t(L.T) + 1);
+  LV_TRY(hipMemcpy(ts.data(), base + L.off_tstart, 4 * ts.size(), hipMemcpyDeviceToHost), "tile_start");
+  if (tile_start) std::memcpy(tile_start, ts.data(), 4 * ts.size());
+  const uint64_t tot = std::min<uint64_t>(ts[L.T], L.cap);
+  if (ids && tot) LV_TRY(hipMemcpy(ids, base + L.off_ids, 4 * tot, hipMemcpyDeviceToHost), "ids");
+  if (codes || rects || vis) {
+    const size_t nr = size_t(L.n) * size_t(L.V);
+    std::vector<lv::Rec> rec(nr);
+    if (nr) LV_TRY(hipMemcpy(rec.data(), base + L.off_rec, sizeof(lv::Rec) * nr, hipMemcpyDeviceToHost), "records");
+    for (size_t r = 0; r < nr; ++r) {
+      const bool on = (rec[r].flags & 8u) != 0;
+      if (vis) vis[r] = on ? 1 : 0;
+      if (codes) codes[r] = on ? (uint64_t(rec[r].code_hi) << 32 | rec[r].code_lo) : 0;
+      if (rects) {
+        rects[4 * r + 0] = on ? int32_t(rec[r].xr & 0xFFFFu) : 0;
+        rects[4 * r + 1] = on ? int32_t(rec[r].xr >> 16) : 0;
+        rects[4 * r + 2] = on ? int32_t(rec[r].yr & 0xFFFFu) : 0;
+        rects[4 * r + 3] = on ? int32_t(rec[r].yr >> 16) : 0;
+      }
+    }
+  }
+  return LV_OK;
+}
+
+uint64_t lv_lf_weight_workspace_size(int32_t n_views) {
+  return n_views > 0 ? lv::loss_ws_bytes(n_views) : 0;
+}
+
+static uint64_t max_view_pixels(const lv_frame* fr) {
+  uint64_t m = 0;
+  for (int v = 0; v < fr->n_views; ++v)
+    m = std::max<uint64_t>(m, uint64_t(fr->cams_host[v].width) * uint64_t(fr->cams_host[v].height));
+  return m;
+}
+
+lv_status lv_lf_weight(lv_context* ctx, const lv_frame* frame, const float* target, float gamma,
+                       int32_t form, float eps, float* weight, void* workspace, hipStream_t stream) {
+  if (!ctx) return LV_ERR_ARG;
+  lv_status s = check_frame(ctx, frame);
+  if (s != LV_OK) return s;
+  if (!target || !weight || !workspace) return fail(ctx, LV_ERR_ARG, "target/weight/workspace NULL");
+  if (form != 0 && form != 1) return fail(ctx, LV_ERR_ARG, "form must be 0 or 1");
+  if (!std::isfinite(gamma) || !std::isfinite(eps) || eps < 0.0f)
+    return fail(ctx, LV_ERR_ARG, "gamma must be finite and eps >= 0");
+  LV_TRY(lv::run_lf_weight(frame->cams_dev, frame->n_views, max_view_pixels(frame), target, gamma,
+                           form, eps, weight, workspace, stream), "lf_weight");
+  return LV_OK;
+}
+
+lv_status lv_l1_grad(lv_context* ctx, const lv_frame* frame, const float* rgb, const float* target,
+                     const float* weight, float* loss, float* d_rgb, hipStream_t stream) {
+  if (!ctx) return LV_ERR_ARG;
+  lv_status s = check_frame(ctx, frame);
+  if (s != LV_OK) return s;
+  if (!rgb || !target || !weight || !loss || !d_rgb)
+    return fail(ctx, LV_ERR_ARG, "rgb/target/weight/loss/d_rgb must be non-NULL");
+  LV_TRY(lv::run_l1_grad(frame->cams_dev, frame->n_views, max_view_pixels(frame), rgb, target,
+                         weight, loss, d_rgb, stream), "l1_grad");
+  return LV_OK;
+}
+
+float lv_gamma_schedule(float t, float total, float t0_frac, float t1_frac, float gamma_max) {
+  const float t0 = t0_frac * total, t1 = t1_frac * total;
+  if (t < t0) return 0.0f;
+  if (t < t1) return gamma_max * (t - t0) / (t1 - t0);
+  return gamma_max;
+}
+
+uint64_t lv_quantile_workspace_size(int64_t n, int32_t n_bins) {
+  if (n < 0 || n_bins < 1 || n_bins > 64) return 0;
+  return lv::quant_ws_bytes(n, n_bins);
+}
+
+lv_status lv_depth_quantile(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
+                            const float* wmax, int32_t n_bins, double q, void* workspace,
+                            float* tau, uint8_t* prune, uint8_t* bins, hipStream_t stream) {
+  if (!ctx) return LV_ERR_ARG;
+  lv_status s = check_voxels(ctx, vox, false);
+  if (s != LV_OK) return s;
+  if ((s = check_frame(ctx, frame)) != LV_OK) return s;
+  if (n_bins < 1 || n_bins > 64) return fail(ctx, LV_ERR_ARG, "n_bins must be in [1, 64]");
+  if (!(q > 0.0 && q <= 1.0)) return fail(ctx, LV_ERR_ARG, "q must be in (0, 1]");
+  if (!workspace || !tau || (vox->n > 0 && (!wmax || !prune)))
+    return fail(ctx, LV_ERR_ARG, "workspace/tau/wmax/prune must be non-NULL");
+  lv::Layout L;
+  lv::RasterArgs a = make_args(L, workspace, vox, frame, nullptr);
+  a.wmax = const_cast<float*>(wmax);
+  LV_TRY(lv::run_depth_quantile(a, n_bins, q, workspace, tau, prune, bins, stream), "depth_quantile");
+  return LV_OK;
+}
+
+lv_status lv_graph_begin(lv_context* ctx, hipStream_t stream) {
+  if (!ctx) return LV_ERR_ARG;
+  if (ctx->capturing) return fail(ctx, LV_ERR_STATE, "already capturing");
+  if (stream == nullptr) return fail(ctx, LV_ERR_ARG, "cannot capture the null stream");
+  LV_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeRelaxed), "begin capture");
+  ctx->capturing = true;
+  return LV_OK;
+}
+
+lv_status lv_graph_end(lv_context* ctx, hipStream_t stream) {
+  if (!ctx) return LV_ERR_ARG;
+  if (!ctx->capturing) return fail(ctx, LV_ERR_STATE, "not capturing");
+  ctx->capturing = false;
+  hipGraph_t g = nullptr;
+  LV_TRY(hipStreamEndCapture(stream, &g), "end capture");
+  if (ctx->exec) { hipGraphExecDestroy(ctx->exec); ctx->exec = nullptr; }
+  if (ctx->graph) { hipGraphDestroy(ctx->graph); ctx->graph = nullptr; }
+  ctx->graph = g;
+  LV_TRY(hipGraphInstantiate(&ctx->exec, g, nullptr, nullptr, 0), "instantiate graph");
+  return LV_OK;
+}
+
+lv_status lv_graph_launch(lv_context* ctx, hipStream_t stream) {
+  if (!ctx) return LV_ERR_ARG;
+  if (!ctx->exec) return fail(ctx, LV_ERR_STATE, "no captured graph");
+  LV_TRY(hipGraphLaunch(ctx->exec, stream), "graph launch");
+  return LV_OK;
+}
+
+lv_status lv_graph_reset(lv_context* ctx) {
+  if (!ctx) return LV_ERR_ARG;
+  if (ctx->exec) { hipGraphExecDestroy(ctx->exec); ctx->exec = nullptr; }
+  if (ctx->graph) { hipGraphDestroy(ctx->graph); ctx->graph = nullptr; }
+  return LV_OK;
+}
+
+lv_status lv_set_timing(lv_context* ctx, int32_t enable) {
+  if (!ctx) return LV_ERR_ARG;
+  ctx->timing = enable != 0;
+  return LV_OK;
+}
+
+lv_status lv_read_timings(lv_context* ctx, double* ms, int64_t* calls) {
+  if (!ctx) return LV_ERR_ARG;
+  for (auto& p : ctx->pending) {
+    if (hipEventSynchronize(p.b) != hipSuccess) return fail(ctx, LV_ERR_HIP, "event sync");
+    float t = 0.0f;
+    if (hipEventElapsedTime(&t, p.a, p.b) == hipSuccess) {
+      ctx->ms[p.phase] += t;
+      ctx->calls[p.phase] += 1;
+    }
+    ctx->pool.push_back(p.a);
+    ctx->pool.push_back(p.b);
+  }
+  ctx->pending.clear();
+  for (int k = 0; k < LV_PH_COUNT; ++k) {
+    if (ms) ms[k] = ctx->ms[k];
+    if (calls) calls[k] = ctx->calls[k];
+    ctx->ms[k] = 0.0;
+    ctx->calls[k] = 0;
+  }
+  return LV_OK;
+}
+
+lv_status lv_autotune(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame, int32_t reps,
+                      lv_settings* best, float* ms_table, hipStream_t stream) {
+  if (!ctx || !best) return LV_ERR_ARG;
+  lv_settings probe;
+  lv_default_settings(&probe);
+  if (best->t_eps > 0.0f) probe.t_eps = best->t_eps;
+  lv::Layout L0;
+  lv_status s = validate_all(ctx, vox, frame, &probe, &L0);
+  if (s != LV_OK) return s;
+  if (reps < 1) reps = 1;
+  const int tiles[3] = {8, 16, 32};
+  const int chunks[3] = {64, 128, 256};
+  const uint64_t P = L0.P;
+  const int64_t n = vox->n;
+  const int nb = 3 * (vox->sh_degree + 1) * (vox->sh_degree + 1);
+  float *rgb = nullptr, *depth = nullptr, *alpha = nullptr, *wmax = nullptr, *drgb = nullptr,
+        *dd = nullptr, *dsh = nullptr;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  lv_status result = LV_OK;
+  float best_ms = -1.0f;
+  auto cleanup = [&]() {
+    hipFree(rgb); hipFree(depth); hipFree(alpha); hipFree(wmax); hipFree(drgb);
+    hipFree(dd); hipFree(dsh); hipFree(ws);
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+  };
+  bool ok = hipMalloc(&rgb, 12 * P) == hipSuccess && hipMalloc(&depth, 4 * P) == hipSuccess &&
+            hipMalloc(&alpha, 4 * P) == hipSuccess && hipMalloc(&drgb, 12 * P) == hipSuccess &&
+            hipMalloc(&wmax, 4 * size_t(n > 0 ? n : 1)) == hipSuccess &&
+            hipMalloc(&dd, 32 * size_t(n > 0 ? n : 1)) == hipSuccess &&
+            hipMalloc(&dsh, 4 * size_t(nb) * size_t(n > 0 ? n : 1)) == hipSuccess &&
+            hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+  if (!ok) { cleanup(); return fail(ctx, LV_ERR_HIP, "autotune: allocation failed"); }
+  // a small non-zero upstream gradient so the backward does its full work
+  lv::launch_fill_u32(reinterpret_cast<uint32_t*>(drgb), 3 * P, 0x358637bdu /* 1e-6f */, stream);
+  lv::launch_fill_u32(reinterpret_cast<uint32_t*>(wmax), uint64_t(n > 0 ? n : 1), 0u, stream);
+  const bool was_timing = ctx->timing;
+  ctx->timing = false;
+  for (int ti = 0; ti < 3 && result == LV_OK; ++ti) {
+    lv_settings st = probe;
+    st.tile = tiles[ti];
+    uint64_t cap = std::max<uint64_t>(1u << 20, 2ull * uint64_t(n) * uint64_t(frame->n_views));
+    cap = std::min<uint64_t>(cap, 0xFFFFFFFFull);
+    uint64_t needed = 0;
+    for (int attempt = 0; attempt < 2; ++attempt) {
+      st.pair_capacity = cap;
+      lv::Layout L;
+      validate_all(ctx, vox, frame, &st, &L);
+      if (L.total > ws_bytes) {
+        hipFree(ws);
+        ws = nullptr;
+        if (hipMalloc(&ws, L.total) != hipSuccess) { result = fail(ctx, LV_ERR_HIP, "autotune: workspace"); break; }
+        ws_bytes = L.total;
+      }
+      if ((s = lv_forward(ctx, vox, frame, &st, ws, rgb, depth, alpha, wmax, stream)) != LV_OK) { result = s; break; }
+      s = lv_check_overflow(ctx, vox, frame, &st, ws, &needed, stream);
+      if (s == LV_OK) break;
+      if (s != LV_ERR_CAPACITY) { result = s; break; }
+      cap = std::min<uint64_t>(needed + needed / 16 + 1024, 0xFFFFFFFFull);
+    }
+    if (result != LV_OK) break;
+    for (int ci = 0; ci < 3; ++ci) {
+      st.chunk = chunks[ci];
+      float ms = 0.0f;
+      // warm-up, then timed repetitions of forward + backward
+      bool run_ok = true;
+      for (int r = -1; r < reps && run_ok; ++r) {
+        if (r == 0) hipEventRecord(e0, stream);
+        run_ok = lv_forward(ctx, vox, frame, &st, ws, rgb, depth, alpha, wmax, stream) == LV_OK &&
+                 lv_backward(ctx, vox, frame, &st, ws, drgb, nullptr, nullptr, dd, dsh, stream) == LV_OK;
+      }
+      hipEventRecord(e1, stream);
+      if (hipEventSynchronize(e1) != hipSuccess) run_ok = false;
+      if (run_ok) hipEventElapsedTime(&ms, e0, e1);
+      ms = run_ok ? ms / reps : -1.0f;
+      if (ms_table) ms_table[ti * 3 + ci] = ms;
+      if (run_ok && (best_ms < 0.0f || ms < best_ms)) {
+        best_ms = ms;
+        *best = st;
+        best->pair_capacity = std::min<uint64_t>(needed + needed / 16 + 1024, 0xFFFFFFFFull);
+      }
+    }
+  }
+  ctx->timing = was_timing;
+  cleanup();
+  if (result == LV_OK && best_ms < 0.0f) result = fail(ctx, LV_ERR_HIP, "autotune: no configuration ran");
+  return result;
+}
+
+}  // extern "C"

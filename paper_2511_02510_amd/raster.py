@@ -1,0 +1,366 @@
+"""Thin Python binding of liblitevoxel (argument marshalling only).
+
+Device memory and streams come from PyTorch; every step of the rasterizer runs
+in the library's HIP kernels.  Function names follow the C-ABI
+(lv_forward -> forward, ...).  The only host logic here is bookkeeping: the
+pair-capacity re-plan after lv_check_overflow and the torch.autograd.Function
+that pairs lv_forward with lv_backward.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _abi
+from ._abi import LvCamera, LvFrame, LvSettings, LvVoxels
+
+
+class LiteVoxelError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(msg)
+        self.status = status
+
+
+def _p(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Context:
+    """An lv_context bound to one HIP device."""
+
+    def __init__(self, device: int = 0):
+        self.lib = _abi.lib()
+        h = ctypes.c_void_p()
+        s = self.lib.lv_create(ctypes.byref(h), int(device))
+        if s != _abi.LV_OK:
+            raise LiteVoxelError(s, f"lv_create(device={device}): "
+                                 f"{self.lib.lv_status_str(s).decode()}")
+        self.h = h
+        self.device = torch.device("cuda", int(device))
+
+    def check(self, s: int, what: str):
+        if s != _abi.LV_OK:
+            msg = self.lib.lv_last_error(self.h).decode()
+            raise LiteVoxelError(s, f"{what}: {self.lib.lv_status_str(s).decode()}: {msg}")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.lv_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Voxels:
+    """Voxel leaves in device memory (structure of arrays)."""
+
+    def __init__(self, ijk: torch.Tensor, level: torch.Tensor, density: torch.Tensor,
+                 sh: torch.Tensor, root_min, root_size: float, sh_degree: int):
+        self.ijk, self.level, self.density, self.sh = ijk, level, density, sh
+        self.root_min = [float(x) for x in root_min]
+        self.root_size = float(root_size)
+        self.sh_degree = int(sh_degree)
+        self.n = int(level.shape[0])
+        self.struct = self._make(density, sh)
+
+    def _make(self, density, sh) -> LvVoxels:
+        s = LvVoxels()
+        s.n = self.n
+        s.sh_degree = self.sh_degree
+        s.root_min = (ctypes.c_float * 3)(*self.root_min)
+        s.root_size = self.root_size
+        s.ijk = self.ijk.data_ptr() if self.n else None
+        s.level = self.level.data_ptr() if self.n else None
+        s.density = density.data_ptr() if self.n else None
+        s.sh = sh.data_ptr() if self.n else None
+        return s
+
+    def with_params(self, density: torch.Tensor, sh: torch.Tensor) -> "Voxels":
+        v = Voxels.__new__(Voxels)
+        v.__dict__.update(self.__dict__)
+        v.density, v.sh = density, sh
+        v.struct = v._make(density, sh)
+        return v
+
+    @staticmethod
+    def from_scene(scene, device) -> "Voxels":
+        dev = torch.device(device)
+        ijk = torch.from_numpy(np.ascontiguousarray(scene.ijk).view(np.int16)).to(dev)
+        level = torch.from_numpy(np.ascontiguousarray(scene.level)).to(dev)
+        dens = torch.from_numpy(np.ascontiguousarray(scene.density, dtype=np.float32)).to(dev)
+        sh = torch.from_numpy(np.ascontiguousarray(scene.sh, dtype=np.float32)).to(dev)
+        return Voxels(ijk, level, dens, sh, scene.root_min, scene.root_size, scene.sh_degree)
+
+
+class Frame:
+    """A batch of pinhole views (host copy for planning, device copy for kernels)."""
+
+    def __init__(self, cams: Sequence, device, bg=(0.0, 0.0, 0.0)):
+        self.n_views = len(cams)
+        self.host = (LvCamera * self.n_views)()
+        for i, c in enumerate(cams):
+            self._fill(self.host[i], c)
+        raw = np.frombuffer(bytes(self.host), dtype=np.uint8).copy()
+        self.dev = torch.from_numpy(raw).to(torch.device(device))
+        self.sizes = [(int(c.width), int(c.height)) for c in cams]
+        self.off = np.zeros(self.n_views + 1, dtype=np.int64)
+        for i, (w, h) in enumerate(self.sizes):
+            self.off[i + 1] = self.off[i] + w * h
+        self.P = int(self.off[-1])
+        self.struct = LvFrame()
+        self.struct.n_views = self.n_views
+        self.struct.cams_host = ctypes.cast(self.host, ctypes.POINTER(LvCamera))
+        self.struct.cams_dev = self.dev.data_ptr()
+        self.struct.bg = (ctypes.c_float * 3)(*[float(x) for x in bg])
+
+    @staticmethod
+    def _fill(dst: LvCamera, c):
+        R = np.asarray(c.R, dtype=np.float32).ravel()
+        dst.R = (ctypes.c_float * 9)(*R.tolist())
+        dst.o = (ctypes.c_float * 3)(*np.asarray(c.o, dtype=np.float32).tolist())
+        dst.fx, dst.fy, dst.cx, dst.cy = float(c.fx), float(c.fy), float(c.cx), float(c.cy)
+        dst.width, dst.height = int(c.width), int(c.height)
+
+    def set_poses(self, cams: Sequence):
+        """Replace the cameras in place (same sizes): graph replays read the new poses."""
+        assert len(cams) == self.n_views
+        for i, c in enumerate(cams):
+            assert (int(c.width), int(c.height)) == self.sizes[i], "sizes are fixed"
+            self._fill(self.host[i], c)
+        raw = torch.from_numpy(np.frombuffer(bytes(self.host), dtype=np.uint8).copy())
+        self.dev.copy_(raw, non_blocking=False)
+
+    def view_rgb(self, rgb: torch.Tensor, v: int) -> torch.Tensor:
+        w, h = self.sizes[v]
+        return rgb[3 * self.off[v]:3 * self.off[v + 1]].view(3, h, w)
+
+
+def settings(tile=16, chunk=64, t_eps=1e-6, pair_capacity=0) -> LvSettings:
+    s = LvSettings()
+    s.tile, s.chunk, s.t_eps, s.pair_capacity = int(tile), int(chunk), float(t_eps), int(pair_capacity)
+    return s
+
+
+# --------------------------------------------------------------- C-ABI calls
+
+def query_sizes(ctx: Context, vox: Voxels, frame: Frame, st: LvSettings) -> int:
+    out = ctypes.c_uint64()
+    ctx.check(ctx.lib.lv_query_sizes(ctx.h, ctypes.byref(vox.struct), ctypes.byref(frame.struct),
+                                     ctypes.byref(st), ctypes.byref(out)), "lv_query_sizes")
+    return int(out.value)
+
+
+def forward(ctx, vox, frame, st, workspace, rgb, depth, alpha, wmax, stream=None):
+    ctx.check(ctx.lib.lv_forward(ctx.h, ctypes.byref(vox.struct), ctypes.byref(frame.struct),
+                                 ctypes.byref(st), _p(workspace), _p(rgb), _p(depth), _p(alpha),
+                                 _p(wmax), _stream(stream)), "lv_forward")
+
+
+def backward(ctx, vox, frame, st, workspace, d_rgb, d_depth, d_alpha, d_density, d_sh, stream=None):
+    ctx.check(ctx.lib.lv_backward(ctx.h, ctypes.byref(vox.struct), ctypes.byref(frame.struct),
+                                  ctypes.byref(st), _p(workspace), _p(d_rgb), _p(d_depth),
+                                  _p(d_alpha), _p(d_density), _p(d_sh), _stream(stream)),
+              "lv_backward")
+
+
+def check_overflow(ctx, vox, frame, st, workspace, stream=None):
+    """(fits, pairs_needed); synchronises the stream."""
+    need = ctypes.c_uint64()
+    s = ctx.lib.lv_check_overflow(ctx.h, ctypes.byref(vox.struct), ctypes.byref(frame.struct),
+                                  ctypes.byref(st), _p(workspace), ctypes.byref(need),
+                                  _stream(stream))
+    if s == _abi.LV_ERR_CAPACITY:
+        return False, int(need.value)
+    ctx.check(s, "lv_check_overflow")
+    return True, int(need.value)
+
+
+def export_bins(ctx, vox, frame, st, workspace, stream=None):
+    """Host copies of the binning state: dict(tile_start, ids, codes, rects, vis)."""
+    T = 0
+    for (w, h) in frame.sizes:
+        T += ((w + st.tile - 1) // st.tile) * ((h + st.tile - 1) // st.tile)
+    ts = np.zeros(T + 1, dtype=np.uint32)
+    nr = vox.n * frame.n_views
+    codes = np.zeros(nr, dtype=np.uint64)
+    rects = np.zeros((nr, 4), dtype=np.int32)
+    vis = np.zeros(nr, dtype=np.uint8)
+    cap = int(st.pair_capacity)
+    ids = np.zeros(max(cap, 1), dtype=np.uint32)
+    ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    ctx.check(ctx.lib.lv_export_bins(ctx.h, ctypes.byref(vox.struct), ctypes.byref(frame.struct),
+                                     ctypes.byref(st), _p(workspace), ptr(ts), ptr(ids), ptr(codes),
+                                     ptr(rects), ptr(vis), _stream(stream)), "lv_export_bins")
+    tot = min(int(ts[-1]), cap)
+    return dict(tile_start=ts.astype(np.int64), ids=ids[:tot].astype(np.int64),
+                codes=codes.reshape(frame.n_views, vox.n), rects=rects.reshape(frame.n_views, vox.n, 4),
+                vis=vis.reshape(frame.n_views, vox.n))
+
+
+def lf_weight_workspace_size(n_views: int) -> int:
+    return int(_abi.lib().lv_lf_weight_workspace_size(int(n_views)))
+
+
+def lf_weight(ctx, frame, target, gamma, form, eps, weight, workspace, stream=None):
+    ctx.check(ctx.lib.lv_lf_weight(ctx.h, ctypes.byref(frame.struct), _p(target), float(gamma),
+                                   int(form), float(eps), _p(weight), _p(workspace),
+                                   _stream(stream)), "lv_lf_weight")
+
+
+def l1_grad(ctx, frame, rgb, target, weight, loss, d_rgb, stream=None):
+    ctx.check(ctx.lib.lv_l1_grad(ctx.h, ctypes.byref(frame.struct), _p(rgb), _p(target),
+                                 _p(weight), _p(loss), _p(d_rgb), _stream(stream)), "lv_l1_grad")
+
+
+def gamma_schedule(t, total, t0_frac=0.3, t1_frac=0.6, gamma_max=0.6) -> float:
+    return float(_abi.lib().lv_gamma_schedule(float(t), float(total), float(t0_frac),
+                                              float(t1_frac), float(gamma_max)))
+
+
+def quantile_workspace_size(n: int, n_bins: int) -> int:
+    return int(_abi.lib().lv_quantile_workspace_size(int(n), int(n_bins)))
+
+
+def depth_quantile(ctx, vox, frame, wmax, n_bins, q, workspace, tau, prune, bins=None, stream=None):
+    ctx.check(ctx.lib.lv_depth_quantile(ctx.h, ctypes.byref(vox.struct), ctypes.byref(frame.struct),
+                                        _p(wmax), int(n_bins), float(q), _p(workspace), _p(tau),
+                                        _p(prune), _p(bins), _stream(stream)), "lv_depth_quantile")
+
+
+def graph_begin(ctx, stream):
+    ctx.check(ctx.lib.lv_graph_begin(ctx.h, _stream(stream)), "lv_graph_begin")
+
+
+def graph_end(ctx, stream):
+    ctx.check(ctx.lib.lv_graph_end(ctx.h, _stream(stream)), "lv_graph_end")
+
+
+def graph_launch(ctx, stream=None):
+    ctx.check(ctx.lib.lv_graph_launch(ctx.h, _stream(stream)), "lv_graph_launch")
+
+
+def graph_reset(ctx):
+    ctx.check(ctx.lib.lv_graph_reset(ctx.h), "lv_graph_reset")
+
+
+def autotune(ctx, vox, frame, reps=3, t_eps=1e-6, stream=None):
+    """-> (best LvSettings, ms table [3 tiles x 3 chunks])."""
+    best = settings(t_eps=t_eps)
+    table = (ctypes.c_float * 9)()
+    ctx.check(ctx.lib.lv_autotune(ctx.h, ctypes.byref(vox.struct), ctypes.byref(frame.struct),
+                                  int(reps), ctypes.byref(best), ctypes.cast(table, ctypes.c_void_p),
+                                  _stream(stream)), "lv_autotune")
+    return best, np.array(list(table), dtype=np.float64).reshape(3, 3)
+
+
+def set_timing(ctx, enable: bool):
+    ctx.check(ctx.lib.lv_set_timing(ctx.h, 1 if enable else 0), "lv_set_timing")
+
+
+def read_timings(ctx):
+    """Synchronises; per-phase (ms, launches) since the last read."""
+    ms = (ctypes.c_double * len(_abi.PHASES))()
+    calls = (ctypes.c_int64 * len(_abi.PHASES))()
+    ctx.check(ctx.lib.lv_read_timings(ctx.h, ctypes.cast(ms, ctypes.c_void_p),
+                                      ctypes.cast(calls, ctypes.c_void_p)), "lv_read_timings")
+    return {name: (ms[i], calls[i]) for i, name in enumerate(_abi.PHASES)}
+
+
+# -------------------------------------------------------- convenience layer
+
+class Renderer:
+    """Owns the workspace of one (voxels, frame, settings) shape and re-plans the
+    pair capacity when lv_check_overflow reports an overflow."""
+
+    def __init__(self, ctx: Context, vox: Voxels, frame: Frame, st: Optional[LvSettings] = None):
+        self.ctx, self.vox, self.frame = ctx, vox, frame
+        self.st = st if st is not None else settings()
+        if self.st.pair_capacity == 0:
+            self.st.pair_capacity = min(max(1 << 20, (3 * vox.n * frame.n_views) // 2), (1 << 32) - 1)
+        self._alloc()
+        self.checked = False
+
+    def _alloc(self):
+        nbytes = query_sizes(self.ctx, self.vox, self.frame, self.st)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.ctx.device)
+
+    def new_outputs(self):
+        d = self.ctx.device
+        P = self.frame.P
+        return (torch.empty(3 * P, device=d), torch.empty(P, device=d), torch.empty(P, device=d))
+
+    def forward(self, rgb, depth, alpha, wmax, vox: Optional[Voxels] = None, stream=None,
+                verify: Optional[bool] = None):
+        vox = vox or self.vox
+        verify = verify or (verify is None and not self.checked)
+        # a truncated pass composites without some occluders, so its weights
+        # are not bounded by the true ones: keep w_max to restore on overflow
+        saved = wmax.clone() if (verify and wmax is not None) else None
+        forward(self.ctx, vox, self.frame, self.st, self.workspace, rgb, depth, alpha, wmax, stream)
+        if verify:
+            fits, need = check_overflow(self.ctx, vox, self.frame, self.st, self.workspace, stream)
+            self.checked = True
+            if not fits:
+                if saved is not None:
+                    wmax.copy_(saved)
+                self.st.pair_capacity = min(need + need // 8 + 4096, (1 << 32) - 1)
+                self._alloc()
+                forward(self.ctx, vox, self.frame, self.st, self.workspace, rgb, depth, alpha,
+                        wmax, stream)
+                fits, need = check_overflow(self.ctx, vox, self.frame, self.st, self.workspace, stream)
+                if not fits:
+                    raise LiteVoxelError(_abi.LV_ERR_CAPACITY, f"{need} pairs do not fit")
+
+    def backward(self, d_rgb, d_depth, d_alpha, d_density, d_sh, vox: Optional[Voxels] = None,
+                 stream=None):
+        backward(self.ctx, vox or self.vox, self.frame, self.st, self.workspace, d_rgb, d_depth,
+                 d_alpha, d_density, d_sh, stream)
+
+
+class RasterizeFn(torch.autograd.Function):
+    """(density [8,N], sh [K,N]) -> (rgb [3P], depth [P], alpha [P]).
+
+    The backward recomputes transmittance back to front inside lv_backward
+    from the per-pixel state lv_forward left in the renderer's workspace
+    (index of the last hit and the transmittance before it): no per-sample
+    state is kept.  w_max is max-accumulated into `wmax` (not differentiable).
+    """
+
+    @staticmethod
+    def forward(ctx, density, sh, renderer: Renderer, wmax: torch.Tensor):
+        vox = renderer.vox.with_params(density.detach().contiguous(), sh.detach().contiguous())
+        rgb, depth, alpha = renderer.new_outputs()
+        renderer.forward(rgb, depth, alpha, wmax, vox=vox)
+        ctx.renderer = renderer
+        ctx.vox = vox
+        ctx.mark_non_differentiable(wmax)
+        return rgb, depth, alpha
+
+    @staticmethod
+    def backward(ctx, g_rgb, g_depth, g_alpha):
+        r = ctx.renderer
+        vox = ctx.vox
+        d_density = torch.empty_like(vox.density)
+        d_sh = torch.empty_like(vox.sh)
+        g_rgb = g_rgb.contiguous() if g_rgb is not None else torch.zeros(3 * r.frame.P, device=vox.density.device)
+        g_depth = g_depth.contiguous() if g_depth is not None else None
+        g_alpha = g_alpha.contiguous() if g_alpha is not None else None
+        r.backward(g_rgb, g_depth, g_alpha, d_density, d_sh, vox=vox)
+        return d_density, d_sh, None, None
+
+
+def rasterize(density, sh, renderer: Renderer, wmax: torch.Tensor):
+    return RasterizeFn.apply(density, sh, renderer, wmax)

@@ -1,0 +1,138 @@
+"""The C-ABI library loads and exports every symbol include/litevoxel.h
+declares; host-only entry points (validation, planning, status strings, the
+gamma ramp) behave as documented.  No device calls: runs without a GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2511_02510_amd import _abi
+from oracle import loss as oracle_loss
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "litevoxel.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(lv_[a-z0-9_]+)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = _abi.lib()
+    names = declared_functions()
+    assert len(names) >= 20
+    for name in names:
+        assert hasattr(lib, name), name
+    # the binding declares exactly the header's functions
+    assert sorted(_abi.symbols()) == names
+
+
+def _vox_frame(n=100, w=64, h=48, views=1):
+    vox = _abi.LvVoxels()
+    vox.n = n
+    vox.sh_degree = 3
+    vox.root_min = (ctypes.c_float * 3)(-1, -1, -1)
+    vox.root_size = 2.0
+    # placeholders: host-only calls never dereference device pointers
+    vox.ijk = vox.level = vox.density = vox.sh = 0x1000
+    cams = (_abi.LvCamera * views)()
+    for i in range(views):
+        c = synth.make_cameras_single(w, h)[0]
+        cams[i].R = (ctypes.c_float * 9)(*c.R.ravel().tolist())
+        cams[i].o = (ctypes.c_float * 3)(*c.o.tolist())
+        cams[i].fx, cams[i].fy, cams[i].cx, cams[i].cy = c.fx, c.fy, c.cx, c.cy
+        cams[i].width, cams[i].height = w, h
+    fr = _abi.LvFrame()
+    fr.n_views = views
+    fr.cams_host = ctypes.cast(cams, ctypes.POINTER(_abi.LvCamera))
+    fr.cams_dev = 0x2000
+    fr._keep = cams
+    st = _abi.LvSettings()
+    _abi.lib().lv_default_settings(ctypes.byref(st))
+    return vox, fr, st
+
+
+def test_default_settings_and_status_strings():
+    lib = _abi.lib()
+    _, _, st = _vox_frame()
+    assert (st.tile, st.chunk, st.pair_capacity) == (16, 64, 0)
+    assert abs(st.t_eps - 1e-6) < 1e-12
+    for s in range(6):
+        assert lib.lv_status_str(s)
+    assert lib.lv_last_error(None) == b""
+
+
+def test_validation_rejects_bad_arguments():
+    lib = _abi.lib()
+    vox, fr, st = _vox_frame()
+    v = lambda: lib.lv_validate(ctypes.byref(vox), ctypes.byref(fr), ctypes.byref(st))
+    assert v() == _abi.LV_OK
+    for field, bad in [("tile", 12), ("chunk", 32), ("t_eps", 1e-3), ("t_eps", 0.0)]:
+        old = getattr(st, field)
+        setattr(st, field, bad)
+        assert v() == _abi.LV_ERR_ARG, field
+        setattr(st, field, old)
+    st.pair_capacity = 1 << 32
+    assert v() == _abi.LV_ERR_ARG
+    st.pair_capacity = 0
+    for field, bad in [("sh_degree", 4), ("n", -1), ("n", 1 << 28), ("root_size", 0.0)]:
+        old = getattr(vox, field)
+        setattr(vox, field, bad)
+        assert v() == _abi.LV_ERR_ARG, field
+        setattr(vox, field, old)
+    vox.density = None
+    assert v() == _abi.LV_ERR_ARG
+    vox.density = 0x1000
+    fr.n_views = 0
+    assert v() == _abi.LV_ERR_ARG
+    fr.n_views = 1
+    fr._keep[0].width = 0
+    assert v() == _abi.LV_ERR_ARG
+    fr._keep[0].width = 64
+    fr._keep[0].fx = float("nan")
+    assert v() == _abi.LV_ERR_ARG
+    fr._keep[0].fx = 50.0
+    assert lib.lv_validate(None, ctypes.byref(fr), ctypes.byref(st)) == _abi.LV_ERR_ARG
+    # an empty scene is valid (background-only render)
+    vox.n = 0
+    vox.ijk = vox.level = vox.density = vox.sh = None
+    assert v() == _abi.LV_OK
+
+
+def test_workspace_planning_scales_with_shapes():
+    lib = _abi.lib()
+    out = ctypes.c_uint64()
+    sizes = []
+    for cap in (0, 1000, 100000):
+        vox, fr, st = _vox_frame(n=5000, w=100, h=70, views=2)
+        st.pair_capacity = cap
+        assert lib.lv_query_sizes(None, ctypes.byref(vox), ctypes.byref(fr), ctypes.byref(st),
+                                  ctypes.byref(out)) == _abi.LV_OK
+        sizes.append(out.value)
+    # 20 bytes of pair buffers per unit of capacity (key, id, merge scratch)
+    assert sizes[2] - sizes[1] == pytest.approx(20 * 99000, abs=3 * 256)
+    # records: 32 B per (view, voxel) + 12 B colour gradient, 48 B per voxel
+    assert sizes[0] > 5000 * 48 + 2 * 5000 * 44
+    assert lib.lv_query_sizes(None, ctypes.byref(vox), ctypes.byref(fr), ctypes.byref(st),
+                              None) == _abi.LV_ERR_ARG
+
+
+def test_aux_workspace_sizes():
+    lib = _abi.lib()
+    assert lib.lv_lf_weight_workspace_size(4) >= 4 * 256 * 4
+    assert lib.lv_lf_weight_workspace_size(0) == 0
+    assert lib.lv_quantile_workspace_size(1000, 16) >= 1000 * 9
+    assert lib.lv_quantile_workspace_size(1000, 65) == 0
+
+
+@pytest.mark.parametrize("t", [0, 1000, 5999, 6000, 9000, 11999, 12000, 15000, 20000])
+def test_gamma_schedule_matches_eq9(t):
+    lib = _abi.lib()
+    got = lib.lv_gamma_schedule(t, 20000, 0.3, 0.6, 0.6)
+    assert abs(got - oracle_loss.gamma_schedule(t, 20000)) < 1e-6
