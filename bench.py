@@ -1,0 +1,249 @@
+"""Benchmark: fwd+bwd megapixels/s of the sparse-voxel tile rasterizer on one
+MI355X, on the 1M-voxel SH3 workload with 8 ring views of uneven resolution.
+
+One step = the whole hot path on one batch of views: projection + binning +
+per-tile sort + composite forward with w_max, inverse-Sobel weights of the
+targets, weighted L1 and its image gradient, composite backward, SH backward
+and the depth-binned w_max quantile cutoff -- all views in one call per
+phase, captured once in a HIP graph and replayed.  Inputs are synthetic
+(seeded) and resident in HBM before timing starts.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "fwd+bwd megapixels/s @1M voxels SH3 (batched vs single-view), % HBM roofline"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+# algorithmic bytes per launch of the composite kernels:
+# per (tile, voxel) pair: 4 B id + 48 B voxel record + 20 B view record;
+# per pixel: forward writes rgb 12 + depth 4 + alpha 4 + saved state 8,
+# backward reads the saved state 8 + d_rgb 12 and writes 11 reduced floats
+# (8 corner densities + 3 colour channels) per pair.
+def composite_bytes(Q, P, which):
+    if which == "composite_fwd":
+        return 72 * Q + 28 * P
+    return 72 * Q + 44 * Q + 20 * P
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="ring1m")
+    ap.add_argument("--tile", type=int, default=0, help="0 = autotune")
+    ap.add_argument("--chunk", type=int, default=64)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-views", type=int, default=1)
+    ap.add_argument("--profile-steps", type=int, default=0,
+                    help="if > 0: only run this many eager steps (for rocprofv3) and exit")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (--gpus {args.gpus} requested): this build "
+              "has no multi-GPU path; run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    import paper_2511_02510_amd as lv
+
+    t0 = time.time()
+    scene, cams, targets = synth.make_config(args.workload)
+    log(f"[bench] workload {args.workload}: N={scene.n} views={len(cams)} "
+        f"sizes={[(c.width, c.height) for c in cams]} ({time.time() - t0:.1f}s)")
+    dev = torch.device("cuda", 0)
+    ctx = lv.Context(0)
+    vox = lv.Voxels.from_scene(scene, dev)
+    frame = lv.Frame(cams, dev)
+    P = frame.P
+    target = torch.from_numpy(np.concatenate([t.ravel() for t in targets]).astype(np.float32)).to(dev)
+
+    if args.tile == 0:
+        best, table = lv.autotune(ctx, vox, frame, reps=3)
+        st = lv.settings(tile=best.tile, chunk=best.chunk, pair_capacity=best.pair_capacity)
+        log(f"[bench] autotune fwd+bwd ms (tile 8/16/32 x chunk 64/128/256):\n{np.round(table, 3)}")
+    else:
+        st = lv.settings(tile=args.tile, chunk=args.chunk)
+    log(f"[bench] settings tile={st.tile} chunk={st.chunk}")
+
+    r = lv.Renderer(ctx, vox, frame, st)
+    rgb, depth, alpha = r.new_outputs()
+    wmax = torch.zeros(vox.n, device=dev)
+    weight = torch.empty(P, device=dev)
+    lw_ws = torch.empty(lv.lf_weight_workspace_size(frame.n_views), dtype=torch.uint8, device=dev)
+    loss = torch.empty(frame.n_views, device=dev)
+    d_rgb = torch.empty(3 * P, device=dev)
+    d_density = torch.empty_like(vox.density)
+    d_sh = torch.empty_like(vox.sh)
+    n_bins, q = 16, 0.1
+    q_ws = torch.empty(lv.quantile_workspace_size(vox.n, n_bins), dtype=torch.uint8, device=dev)
+    tau = torch.empty(n_bins, device=dev)
+    prune = torch.empty(vox.n, dtype=torch.uint8, device=dev)
+    gamma = lv.gamma_schedule(0.5, 1.0)
+
+    stream = torch.cuda.Stream()
+
+    def step(verify=False):
+        r.forward(rgb, depth, alpha, wmax, stream=stream, verify=verify)
+        lv.lf_weight(ctx, frame, target, gamma, 0, 1e-3, weight, lw_ws, stream=stream)
+        lv.l1_grad(ctx, frame, rgb, target, weight, loss, d_rgb, stream=stream)
+        r.backward(d_rgb, None, None, d_density, d_sh, stream=stream)
+        lv.depth_quantile(ctx, vox, frame, wmax, n_bins, q, q_ws, tau, prune, stream=stream)
+
+    with torch.cuda.stream(stream):
+        step(verify=True)           # sizes the pair buffers exactly
+    torch.cuda.synchronize()
+    fits, Q = lv.check_overflow(ctx, vox, frame, r.st, r.workspace, stream=stream)
+    assert fits
+    log(f"[bench] pairs Q={Q} capacity={r.st.pair_capacity}")
+
+    if args.profile_steps > 0:
+        for _ in range(args.profile_steps):
+            step()
+        torch.cuda.synchronize()
+        log("[bench] profile steps done")
+        return
+
+    # ---- per-kernel timing (HIP events on the library's stream), eager
+    lv.set_timing(ctx, True)
+    lv.read_timings(ctx)
+    for _ in range(max(3, args.steps // 2)):
+        step()
+    ph = lv.read_timings(ctx)
+    lv.set_timing(ctx, False)
+    phases = {k: (ms / max(c, 1)) for k, (ms, c) in ph.items()}
+    log("[bench] phase ms/launch: " + ", ".join(f"{k} {v:.3f}" for k, v in phases.items()))
+
+    # ---- graph capture of one whole step
+    lv.graph_begin(ctx, stream)
+    step()
+    lv.graph_end(ctx, stream)
+    for _ in range(args.warmup):
+        lv.graph_launch(ctx, stream)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        lv.graph_launch(ctx, stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    ms_step = 1e3 * elapsed / args.steps
+    value = P * args.steps / elapsed / 1e6
+    log(f"[bench] graph step {ms_step:.3f} ms -> {value:.1f} MP/s fwd+bwd")
+
+    # ---- forward-only graph
+    lv.graph_reset(ctx)
+    lv.graph_begin(ctx, stream)
+    r.forward(rgb, depth, alpha, wmax, stream=stream, verify=False)
+    lv.graph_end(ctx, stream)
+    for _ in range(args.warmup):
+        lv.graph_launch(ctx, stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        lv.graph_launch(ctx, stream)
+    torch.cuda.synchronize()
+    fwd_ms = 1e3 * (time.perf_counter() - t1) / args.steps
+    lv.graph_reset(ctx)
+
+    # ---- single-view plain path: each view alone, eager, no graph
+    single = []
+    for v, c in enumerate(cams):
+        f1 = lv.Frame([c], dev)
+        r1 = lv.Renderer(ctx, vox, f1, lv.settings(tile=st.tile, chunk=st.chunk))
+        o = r1.new_outputs()
+        w1 = torch.empty(f1.P, device=dev)
+        lw1 = torch.empty(lv.lf_weight_workspace_size(1), dtype=torch.uint8, device=dev)
+        tg = target[3 * int(frame.off[v]):3 * int(frame.off[v + 1])]
+        l1 = torch.empty(1, device=dev)
+        g1 = torch.empty(3 * f1.P, device=dev)
+
+        def one(verify=False):
+            r1.forward(*o, wmax, stream=stream, verify=verify)
+            lv.lf_weight(ctx, f1, tg, gamma, 0, 1e-3, w1, lw1, stream=stream)
+            lv.l1_grad(ctx, f1, o[0], tg, w1, l1, g1, stream=stream)
+            r1.backward(g1, None, None, d_density, d_sh, stream=stream)
+
+        one(verify=True)
+        for _ in range(2):
+            one()
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        reps = max(3, args.steps // 4)
+        for _ in range(reps):
+            one()
+        torch.cuda.synchronize()
+        single.append(1e3 * (time.perf_counter() - ts) / reps)
+    log(f"[bench] single-view plain fwd+bwd ms: {np.round(single, 3).tolist()}")
+
+    # ---- roofline of the dominant kernel
+    dom = max(("composite_fwd", "composite_bwd"), key=lambda k: phases[k])
+    alg = composite_bytes(Q, P, dom)
+    achieved = alg / (phases[dom] * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+            "alg_bytes_per_launch": int(alg), "ms_per_launch": round(phases[dom], 4)}
+    fwd_alg = composite_bytes(Q, P, "composite_fwd")
+    fwd_roof = fwd_alg / (phases["composite_fwd"] * 1e-3) / 1e9
+
+    # ---- CPU baseline: the oracle on a bounded sample (the first views)
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        nv = max(1, min(args.cpu_sample_views, len(cams)))
+        sub = cams[:nv]
+        rng = np.random.default_rng(0)
+        Ps = sum(c.npix for c in sub)
+        g = rng.normal(0, 1e-3, 3 * Ps)
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        tc = time.perf_counter()
+        oracle.render(scene, sub, threads=threads)
+        oracle.backward(scene, sub, g, threads=threads)
+        dt = time.perf_counter() - tc
+        cpu = {"value": round(Ps / dt / 1e6, 4), "unit": "MP/s", "cores": threads, "kind": "oracle",
+               "sample": f"fwd+bwd of view(s) 0..{nv - 1} ({Ps} px) of the same workload, FP64, "
+                         f"{dt:.1f} s"}
+        log(f"[bench] oracle {cpu}")
+
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "MP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {scene.n} voxels (octree levels 7-11, shell + 10% "
+                               f"clutter), SH degree 3, {len(cams)} ring views "
+                               f"{[(c.width, c.height) for c in cams]}, {P} px per step",
+                   "tile": int(st.tile), "chunk": int(st.chunk), "pairs": int(Q)},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "fwd_mp_s": round(P / fwd_ms / 1e3, 2),
+        "fwd_ms": round(fwd_ms, 4),
+        "fwd_composite_hbm_frac": round(fwd_roof / HBM_PEAK_GBS, 4),
+        "per_view_ms_batched": round(ms_step / len(cams), 4),
+        "single_view_plain_ms": [round(x, 4) for x in single],
+        "phases_ms": {k: round(v, 4) for k, v in phases.items()},
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

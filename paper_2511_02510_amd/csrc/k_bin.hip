@@ -364,12 +364,25 @@ __global__ void k_order_scan(RasterArgs a) {
   }
 }
 
+// Ranks are taken in LDS and each block reserves one range per bucket with a
+// single global atomic (one global atomic per tile contends on the few bucket
+// counters).
 __global__ __launch_bounds__(256) void k_order_scatter(RasterArgs a) {
+  __shared__ uint32_t lc[32], lb[32];
+  if (threadIdx.x < 32) lc[threadIdx.x] = 0u;
+  __syncthreads();
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= a.T) return;
-  const int b = len_bucket(tile_len(a, t));
-  const uint32_t pos = a.ws.counters[C_BSTART + b] + atomicAdd(&a.ws.counters[C_BFILL + b], 1u);
-  a.ws.torder[pos] = t;
+  int b = -1;
+  uint32_t local = 0;
+  if (t < a.T) {
+    b = len_bucket(tile_len(a, t));
+    local = atomicAdd(&lc[b], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x < 32 && lc[threadIdx.x])
+    lb[threadIdx.x] = atomicAdd(&a.ws.counters[C_BFILL + threadIdx.x], lc[threadIdx.x]);
+  __syncthreads();
+  if (b >= 0) a.ws.torder[a.ws.counters[C_BSTART + b] + lb[b] + local] = t;
 }
 
 hipError_t launch_order(const RasterArgs& a, hipStream_t s) {

@@ -19,7 +19,8 @@
 // non-negative float, exact and order-independent) and then flushed with one
 // global atomic max per (tile, voxel).  Backward gradients (8 corner
 // densities + 3 colour channels per voxel) are pre-reduced per chunk in LDS
-// and flushed with one global atomic add per (tile, voxel, component).
+// (in lane-spread copies, see the backward kernel) and flushed with one global
+// atomic add per (tile, voxel, component).
 #include "lv_common.h"
 
 namespace lv {
@@ -118,7 +119,9 @@ __device__ __forceinline__ uint32_t span_bits(uint32_t range, int org) {
   return ((2u << h) - 1u) & ~((1u << l) - 1u);
 }
 
-// candidate mask of this lane for voxels [64 w, 64 w + 64) of the chunk
+// Candidate mask of this lane for voxels [64 w, 64 w + 64) of the chunk: one
+// 64-bit ballot per pixel row and per pixel column of the wave's 8 x 8 block,
+// AND-ed for the lane's own row and column.
 template <int CH>
 __device__ __forceinline__ unsigned long long lane_mask(const Stage<CH>& S, int w, int bx, int by,
                                                         int lx, int ly) {
@@ -197,8 +200,36 @@ __device__ __forceinline__ float opacity(float tau, float ex) {
   return 1.0f - ex;
 }
 
+
 // ======================================================================
 // forward
+struct FwdState {
+  float T, C0, C1, C2, D, Tpre;
+  uint32_t nlast;
+  bool done;
+};
+
+// one fragment (this lane's pixel, voxel jj at list position pos); returns w_k
+template <int CH>
+__device__ __forceinline__ float fwd_fragment(const Stage<CH>& S, int jj, uint32_t pos,
+                                              const Ray& ray, FwdState& st, float t_eps) {
+  const Seg sg = slab(S, jj, ray);
+  if (!sg.hit) return 0.0f;
+  const Quad q = quad(S, jj, ray, sg);
+  const float ex = __expf(-q.tau);
+  const float al = opacity(q.tau, ex);
+  const float wk = st.T * al;
+  st.C0 = fmaf(wk, S.col[0][jj], st.C0);
+  st.C1 = fmaf(wk, S.col[1][jj], st.C1);
+  st.C2 = fmaf(wk, S.col[2][jj], st.C2);
+  st.D = fmaf(wk, q.tm, st.D);
+  st.Tpre = st.T;
+  st.nlast = pos + 1u;
+  st.T = st.T * ex;
+  if (st.T < t_eps) st.done = true;
+  return wk;
+}
+
 template <int TS, int NW>
 __global__ __launch_bounds__(TS* TS) void k_composite_fwd(RasterArgs a) {
   constexpr int NT = TS * TS;
@@ -233,9 +264,9 @@ __global__ __launch_bounds__(TS* TS) void k_composite_fwd(RasterArgs a) {
     const uint32_t count = uint32_t(s1 - s0);
     const uint32_t* ids = a.ws.ids + s0;
 
-    float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, D = 0.0f, Tpre = 1.0f;
-    uint32_t nlast = 0;
-    bool done = !inimg;
+    FwdState st;
+    st.T = 1.0f; st.C0 = st.C1 = st.C2 = 0.0f; st.D = 0.0f; st.Tpre = 1.0f;
+    st.nlast = 0; st.done = !inimg;
     for (uint32_t cb = 0; cb < count; cb += CH) {
       const uint32_t nc = (count - cb) < uint32_t(CH) ? (count - cb) : uint32_t(CH);
       stage_chunk<CH, NT>(S, a, ids, cb, nc, v, o);
@@ -245,25 +276,13 @@ __global__ __launch_bounds__(TS* TS) void k_composite_fwd(RasterArgs a) {
       for (int w = 0; w < NW; ++w) {
         if (uint32_t(w * 64) >= nc) break;
         unsigned long long m = lane_mask(S, w, bx, by, lx, ly);
-        if (done) m = 0;
+        if (st.done) m = 0;
         while (m) {
           const int jj = w * 64 + __builtin_ctzll(m);
           m &= m - 1;
-          const Seg sg = slab(S, jj, ray);
-          if (!sg.hit) continue;
-          const Quad q = quad(S, jj, ray, sg);
-          const float ex = __expf(-q.tau);
-          const float al = opacity(q.tau, ex);
-          const float wk = T * al;
-          C0 = fmaf(wk, S.col[0][jj], C0);
-          C1 = fmaf(wk, S.col[1][jj], C1);
-          C2 = fmaf(wk, S.col[2][jj], C2);
-          D = fmaf(wk, q.tm, D);
-          atomicMax(&s_wmax[jj], __float_as_uint(wk));
-          Tpre = T;
-          nlast = cb + uint32_t(jj) + 1u;
-          T = T * ex;
-          if (T < a.t_eps) { done = true; m = 0; }
+          const float wk = fwd_fragment(S, jj, cb + uint32_t(jj), ray, st, a.t_eps);
+          if (wk > 0.0f) atomicMax(&s_wmax[jj], __float_as_uint(wk));
+          if (st.done) m = 0;
         }
       }
       __syncthreads();
@@ -271,20 +290,20 @@ __global__ __launch_bounds__(TS* TS) void k_composite_fwd(RasterArgs a) {
         const uint32_t u = s_wmax[k];
         if (u) atomicMax(reinterpret_cast<unsigned int*>(a.wmax) + S.id[k], u);
       }
-      if (__syncthreads_and(done ? 1 : 0)) break;
+      if (__syncthreads_and(st.done ? 1 : 0)) break;
     }
     if (inimg) {
       const uint64_t local = uint64_t(py) * uint64_t(vt.W) + uint64_t(px);
       const uint64_t npv = uint64_t(vt.W) * uint64_t(vt.H);
       const uint64_t g = vt.pix_base + local;
       float* rgb = a.rgb + 3 * vt.pix_base + local;
-      rgb[0] = fmaf(T, a.bg[0], C0);
-      rgb[npv] = fmaf(T, a.bg[1], C1);
-      rgb[2 * npv] = fmaf(T, a.bg[2], C2);
-      a.depth[g] = D;
-      a.alpha[g] = 1.0f - T;
-      a.ws.nlast[g] = nlast;
-      a.ws.tpre[g] = Tpre;
+      rgb[0] = fmaf(st.T, a.bg[0], st.C0);
+      rgb[npv] = fmaf(st.T, a.bg[1], st.C1);
+      rgb[2 * npv] = fmaf(st.T, a.bg[2], st.C2);
+      a.depth[g] = st.D;
+      a.alpha[g] = 1.0f - st.T;
+      a.ws.nlast[g] = st.nlast;
+      a.ws.tpre[g] = st.Tpre;
     }
   }
 }
@@ -297,17 +316,90 @@ __global__ __launch_bounds__(TS* TS) void k_composite_fwd(RasterArgs a) {
 //   dL/dcolour_k     += w_k g_C
 // T_{k-1} = T_k exp(tau_k), starting from the transmittance saved before the
 // last hit, so no per-sample state is stored.
+//
+// Accumulation: the 11 contributions of a fragment are added with LDS atomics
+// into one of NC copies of the voxel's accumulator, chosen by lane & (NC-1),
+// so that the many lanes covered by one large voxel do not all serialise on
+// the same LDS address; the copies are summed when the chunk is flushed to
+// global memory.
+struct BwdState {
+  float Tb;            // transmittance before the hit processed last
+  float gC0, gC1, gC2, gD, gA;
+  float base, SC0, SC1, SC2, SD;
+  bool first;
+};
+
+// one fragment; writes the 11 gradient contributions into g, returns hit
+template <int CH>
+__device__ __forceinline__ bool bwd_fragment(const Stage<CH>& S, int jj, const Ray& ray,
+                                             BwdState& st, const float bg[3], float g[11]) {
+  const Seg sg = slab(S, jj, ray);
+  if (!sg.hit) return false;
+  const Quad q = quad(S, jj, ray, sg);
+  const float ex = __expf(-q.tau);
+  const float al = opacity(q.tau, ex);
+  float Tafter, Tbefore;
+  if (st.first) {
+    Tbefore = st.Tb;
+    Tafter = st.Tb * ex;
+    st.base = Tafter * (st.gA - (st.gC0 * bg[0] + st.gC1 * bg[1] + st.gC2 * bg[2]));
+    st.first = false;
+  } else {
+    Tafter = st.Tb;
+    Tbefore = st.Tb * __expf(q.tau);
+  }
+  const float wk = Tbefore * al;
+  const float c0 = S.col[0][jj], c1 = S.col[1][jj], c2 = S.col[2][jj];
+  float dtau = st.base + st.gD * (Tafter * q.tm - st.SD);
+  dtau = fmaf(st.gC0, Tafter * c0 - st.SC0, dtau);
+  dtau = fmaf(st.gC1, Tafter * c1 - st.SC1, dtau);
+  dtau = fmaf(st.gC2, Tafter * c2 - st.SC2, dtau);
+  const float gh = dtau * q.hl;
+  {
+    const float x1 = q.ua[0], y1 = q.ua[1], z1 = q.ua[2];
+    const float x0 = 1.0f - x1, y0 = 1.0f - y1, z0 = 1.0f - z1;
+    const float y0z0 = y0 * z0, y1z0 = y1 * z0, y0z1 = y0 * z1, y1z1 = y1 * z1;
+    g[0] = x0 * y0z0; g[1] = x1 * y0z0; g[2] = x0 * y1z0; g[3] = x1 * y1z0;
+    g[4] = x0 * y0z1; g[5] = x1 * y0z1; g[6] = x0 * y1z1; g[7] = x1 * y1z1;
+  }
+  {
+    const float x1 = q.ub[0], y1 = q.ub[1], z1 = q.ub[2];
+    const float x0 = 1.0f - x1, y0 = 1.0f - y1, z0 = 1.0f - z1;
+    const float y0z0 = y0 * z0, y1z0 = y1 * z0, y0z1 = y0 * z1, y1z1 = y1 * z1;
+    g[0] = gh * (g[0] + x0 * y0z0); g[1] = gh * (g[1] + x1 * y0z0);
+    g[2] = gh * (g[2] + x0 * y1z0); g[3] = gh * (g[3] + x1 * y1z0);
+    g[4] = gh * (g[4] + x0 * y0z1); g[5] = gh * (g[5] + x1 * y0z1);
+    g[6] = gh * (g[6] + x0 * y1z1); g[7] = gh * (g[7] + x1 * y1z1);
+  }
+  g[8] = wk * st.gC0;
+  g[9] = wk * st.gC1;
+  g[10] = wk * st.gC2;
+  st.SC0 = fmaf(wk, c0, st.SC0);
+  st.SC1 = fmaf(wk, c1, st.SC1);
+  st.SC2 = fmaf(wk, c2, st.SC2);
+  st.SD = fmaf(wk, q.tm, st.SD);
+  st.Tb = Tbefore;
+  return true;
+}
+
+// copies of each voxel accumulator: LDS for the accumulators stays ~22 KB
+template <int CH>
+struct AccCopies { static constexpr int value = CH <= 64 ? 8 : (CH <= 128 ? 4 : 2); };
+
 template <int TS, int NW>
 __global__ __launch_bounds__(TS* TS) void k_composite_bwd(RasterArgs a) {
   constexpr int NT = TS * TS;
   constexpr int CH = 64 * NW;
   constexpr int BPR = TS / 8;
+  constexpr int NC = AccCopies<CH>::value;
   __shared__ Stage<CH> S;
-  __shared__ float s_g[11][CH];
+  __shared__ float s_g[11][CH][NC];
   __shared__ uint32_t s_tile, s_maxn;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lx = lane & 7, ly = lane >> 3;
+  const int copy = lane & (NC - 1);
   const int wbx = (wave % BPR) * 8, wby = (wave / BPR) * 8;
+  const float bg[3] = {a.bg[0], a.bg[1], a.bg[2]};
 
   for (;;) {
     if (threadIdx.x == 0) {
@@ -332,33 +424,35 @@ __global__ __launch_bounds__(TS* TS) void k_composite_bwd(RasterArgs a) {
     const uint32_t* ids = a.ws.ids + s0;
 
     uint32_t nlast = 0;
-    float Tb = 1.0f, gC0 = 0.0f, gC1 = 0.0f, gC2 = 0.0f, gD = 0.0f, gA = 0.0f;
+    BwdState st;
+    st.Tb = 1.0f; st.gC0 = st.gC1 = st.gC2 = st.gD = st.gA = 0.0f;
+    st.base = st.SC0 = st.SC1 = st.SC2 = st.SD = 0.0f;
+    st.first = true;
     if (inimg) {
       const uint64_t local = uint64_t(py) * uint64_t(vt.W) + uint64_t(px);
       const uint64_t npv = uint64_t(vt.W) * uint64_t(vt.H);
-      const uint64_t g = vt.pix_base + local;
-      nlast = a.ws.nlast[g];
-      Tb = a.ws.tpre[g];
+      const uint64_t gp = vt.pix_base + local;
+      nlast = a.ws.nlast[gp];
+      st.Tb = a.ws.tpre[gp];
       const float* dr = a.d_rgb + 3 * vt.pix_base + local;
-      gC0 = dr[0]; gC1 = dr[npv]; gC2 = dr[2 * npv];
-      gD = a.d_depth ? a.d_depth[g] : 0.0f;
-      gA = a.d_alpha ? a.d_alpha[g] : 0.0f;
+      st.gC0 = dr[0]; st.gC1 = dr[npv]; st.gC2 = dr[2 * npv];
+      st.gD = a.d_depth ? a.d_depth[gp] : 0.0f;
+      st.gA = a.d_alpha ? a.d_alpha[gp] : 0.0f;
     }
     if (nlast) atomicMax(&s_maxn, nlast);
     __syncthreads();
     const uint32_t maxn = s_maxn;
     __syncthreads();
 
-    bool first = true;
-    float base = 0.0f, SC0 = 0.0f, SC1 = 0.0f, SC2 = 0.0f, SD = 0.0f;
     const int nch = int((maxn + CH - 1) / CH);
     for (int ci = nch - 1; ci >= 0; --ci) {
       const uint32_t cb = uint32_t(ci) * CH;
       const uint32_t nc = (maxn - cb) < uint32_t(CH) ? (maxn - cb) : uint32_t(CH);
       stage_chunk<CH, NT>(S, a, ids, cb, nc, v, o);
-      for (int k = threadIdx.x; k < CH; k += NT)
-#pragma unroll
-        for (int c = 0; c < 11; ++c) s_g[c][k] = 0.0f;
+      {
+        float* z = &s_g[0][0][0];
+        for (int k = threadIdx.x; k < 11 * CH * NC; k += NT) z[k] = 0.0f;
+      }
       __syncthreads();
 #pragma unroll 1
       for (int w = NW - 1; w >= 0; --w) {
@@ -368,73 +462,34 @@ __global__ __launch_bounds__(TS* TS) void k_composite_bwd(RasterArgs a) {
         if (lim <= 0) m = 0;
         else if (lim < 64) m &= (1ull << lim) - 1ull;
         while (m) {
-          const int jb = 63 - __builtin_clzll(m);
-          m &= ~(1ull << jb);
-          const int jj = w * 64 + jb;
-          const Seg sg = slab(S, jj, ray);
-          if (!sg.hit) continue;
-          const Quad q = quad(S, jj, ray, sg);
-          const float ex = __expf(-q.tau);
-          const float al = opacity(q.tau, ex);
-          float Tafter, Tbefore;
-          if (first) {
-            Tbefore = Tb;
-            Tafter = Tb * ex;
-            base = Tafter * (gA - (gC0 * a.bg[0] + gC1 * a.bg[1] + gC2 * a.bg[2]));
-            first = false;
-          } else {
-            Tafter = Tb;
-            Tbefore = Tb * __expf(q.tau);
-          }
-          const float wk = Tbefore * al;
-          const float c0 = S.col[0][jj], c1 = S.col[1][jj], c2 = S.col[2][jj];
-          float dtau = base + gD * (Tafter * q.tm - SD);
-          dtau = fmaf(gC0, Tafter * c0 - SC0, dtau);
-          dtau = fmaf(gC1, Tafter * c1 - SC1, dtau);
-          dtau = fmaf(gC2, Tafter * c2 - SC2, dtau);
-          const float gh = dtau * q.hl;
-          // corner weights at both Gauss points
-          float wa[8], wb[8];
-          {
-            const float x1 = q.ua[0], y1 = q.ua[1], z1 = q.ua[2];
-            const float x0 = 1.0f - x1, y0 = 1.0f - y1, z0 = 1.0f - z1;
-            const float y0z0 = y0 * z0, y1z0 = y1 * z0, y0z1 = y0 * z1, y1z1 = y1 * z1;
-            wa[0] = x0 * y0z0; wa[1] = x1 * y0z0; wa[2] = x0 * y1z0; wa[3] = x1 * y1z0;
-            wa[4] = x0 * y0z1; wa[5] = x1 * y0z1; wa[6] = x0 * y1z1; wa[7] = x1 * y1z1;
-          }
-          {
-            const float x1 = q.ub[0], y1 = q.ub[1], z1 = q.ub[2];
-            const float x0 = 1.0f - x1, y0 = 1.0f - y1, z0 = 1.0f - z1;
-            const float y0z0 = y0 * z0, y1z0 = y1 * z0, y0z1 = y0 * z1, y1z1 = y1 * z1;
-            wb[0] = x0 * y0z0; wb[1] = x1 * y0z0; wb[2] = x0 * y1z0; wb[3] = x1 * y1z0;
-            wb[4] = x0 * y0z1; wb[5] = x1 * y0z1; wb[6] = x0 * y1z1; wb[7] = x1 * y1z1;
-          }
+          const int jbit = 63 - __builtin_clzll(m);
+          m &= ~(1ull << jbit);
+          const int jj = w * 64 + jbit;
+          float g[11];
+          if (bwd_fragment(S, jj, ray, st, bg, g)) {
 #pragma unroll
-          for (int c = 0; c < 8; ++c) atomicAdd(&s_g[c][jj], gh * (wa[c] + wb[c]));
-          atomicAdd(&s_g[8][jj], wk * gC0);
-          atomicAdd(&s_g[9][jj], wk * gC1);
-          atomicAdd(&s_g[10][jj], wk * gC2);
-          SC0 = fmaf(wk, c0, SC0);
-          SC1 = fmaf(wk, c1, SC1);
-          SC2 = fmaf(wk, c2, SC2);
-          SD = fmaf(wk, q.tm, SD);
-          Tb = Tbefore;
+            for (int c = 0; c < 11; ++c) atomicAdd(&s_g[c][jj][copy], g[c]);
+          }
         }
       }
       __syncthreads();
       for (uint32_t k = threadIdx.x; k < nc; k += NT) {
         const uint32_t id = S.id[k];
+        float gs[11];
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-          const float g = s_g[c][k];
-          if (g != 0.0f) unsafeAtomicAdd(&a.d_density[size_t(c) * size_t(a.n) + id], g);
+        for (int c = 0; c < 11; ++c) {
+          float s = 0.0f;
+#pragma unroll
+          for (int q = 0; q < NC; ++q) s += s_g[c][k][q];
+          gs[c] = s;
         }
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+          if (gs[c] != 0.0f) unsafeAtomicAdd(&a.d_density[size_t(c) * size_t(a.n) + id], gs[c]);
         float* dc = a.ws.dcol + (size_t(v) * size_t(a.n) + id) * 3;
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-          const float g = s_g[8 + ch][k];
-          if (g != 0.0f) unsafeAtomicAdd(&dc[ch], g);
-        }
+        for (int ch = 0; ch < 3; ++ch)
+          if (gs[8 + ch] != 0.0f) unsafeAtomicAdd(&dc[ch], gs[8 + ch]);
       }
       __syncthreads();
     }
