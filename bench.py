@@ -55,7 +55,21 @@ def main():
     ap.add_argument("--cpu-sample-views", type=int, default=1)
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="if > 0: only run this many eager steps (for rocprofv3) and exit")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="if > 0: only copy this many MiB device-to-device 3 times (a kernel of "
+                         "known traffic that calibrates the HBM byte counters) and exit")
     args = ap.parse_args()
+
+    if args.copy_probe_mib > 0:
+        import torch
+        n = args.copy_probe_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copied {4 * n} bytes x 3")
+        return
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested): this build "

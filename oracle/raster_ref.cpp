@@ -564,6 +564,8 @@ int ref_project_keys(int64_t n, const float* root_min, float root_size,
     float R[9], o[3], fx = c[12], fy = c[13], cx = c[14], cy = c[15];
     for (int k = 0; k < 9; ++k) R[k] = c[k];
     for (int k = 0; k < 3; ++k) o[k] = c[9 + k];
+    // records are independent: one per (view, voxel)
+#pragma omp parallel for schedule(static)
     for (int64_t v = 0; v < n; ++v) {
       size_t r = size_t(vi) * n + v;
       int l = level[v];

@@ -195,7 +195,7 @@ __global__ __launch_bounds__(256) void k_preprocess(RasterArgs a) {
       const uint32_t ty0 = y0 >> sh_ts, ty1 = y1 >> sh_ts;
       for (uint32_t ty = ty0; ty <= ty1; ++ty)
         for (uint32_t tx = tx0; tx <= tx1; ++tx)
-          atomicAdd(&a.ws.tcount[vt.tile_base + ty * vt.tiles_x + tx], 1u);
+          atomicAdd(&a.ws.tcount[uint64_t(i & (kSpread - 1)) * a.T + vt.tile_base + ty * vt.tiles_x + tx], 1u);
     }
     uint4* dst = reinterpret_cast<uint4*>(&a.ws.rec[size_t(v) * size_t(n) + size_t(i)]);
     dst[0] = make_uint4(__float_as_uint(rec.r), __float_as_uint(rec.g), __float_as_uint(rec.b),
@@ -252,7 +252,8 @@ __device__ unsigned long long block_incl_scan(unsigned long long x, unsigned lon
 
 __global__ __launch_bounds__(kScanBlock) void k_scan_reduce(RasterArgs a) {
   const uint64_t t = uint64_t(blockIdx.x) * kScanBlock + threadIdx.x;
-  unsigned long long x = t < a.T ? a.ws.tcount[t] : 0u;
+  const uint64_t n = uint64_t(a.T) * kSpread;
+  unsigned long long x = t < n ? a.ws.tcount[(t % kSpread) * a.T + t / kSpread] : 0u;
   unsigned long long tot;
   block_incl_scan(x, &tot);
   if (threadIdx.x == 0) reinterpret_cast<unsigned long long*>(a.ws.bsum)[blockIdx.x] = tot;
@@ -277,15 +278,15 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_top(RasterArgs a, uint32_t 
 
 __global__ __launch_bounds__(kScanBlock) void k_scan_down(RasterArgs a) {
   const uint64_t t = uint64_t(blockIdx.x) * kScanBlock + threadIdx.x;
-  unsigned long long x = t < a.T ? a.ws.tcount[t] : 0u;
+  const uint64_t n = uint64_t(a.T) * kSpread;
+  const uint64_t ci = (t % kSpread) * a.T + t / kSpread;   // counter of scan position t
+  unsigned long long x = t < n ? a.ws.tcount[ci] : 0u;
   unsigned long long tot;
   unsigned long long inc = block_incl_scan(x, &tot);
   const unsigned long long ex =
       reinterpret_cast<const unsigned long long*>(a.ws.bsum)[blockIdx.x] + inc - x;
-  if (t <= a.T) {
-    a.ws.tstart[t] = ex > 0xFFFFFFFFull ? 0xFFFFFFFFu : uint32_t(ex);
-    a.ws.tfill[t] = 0u;
-  }
+  if (t <= n) a.ws.tstart[t] = ex > 0xFFFFFFFFull ? 0xFFFFFFFFu : uint32_t(ex);
+  if (t < n) a.ws.tfill[ci] = 0u;
 }
 
 hipError_t launch_scan_tiles(const RasterArgs& a, uint32_t nblk, hipStream_t s) {
@@ -315,8 +316,9 @@ __global__ __launch_bounds__(256) void k_emit(RasterArgs a) {
   for (uint32_t ty = (y0 >> sh_ts); ty <= (y1 >> sh_ts); ++ty)
     for (uint32_t tx = (x0 >> sh_ts); tx <= (x1 >> sh_ts); ++tx) {
       const uint32_t gt = vt.tile_base + ty * vt.tiles_x + tx;
-      const uint32_t slot = atomicAdd(&a.ws.tfill[gt], 1u);
-      const uint64_t pos = uint64_t(a.ws.tstart[gt]) + slot;
+      const uint32_t sub = uint32_t(i & (kSpread - 1));
+      const uint32_t slot = atomicAdd(&a.ws.tfill[uint64_t(sub) * a.T + gt], 1u);
+      const uint64_t pos = uint64_t(a.ws.tstart[uint64_t(gt) * kSpread + sub]) + slot;
       if (pos < a.cap) a.ws.pairs[pos] = key;
     }
 }
@@ -332,8 +334,8 @@ hipError_t launch_emit(const RasterArgs& a, hipStream_t s) {
 // Persistent composite kernels pop tiles longest list first: tiles are
 // counting-sorted by floor(log2(count)) (bucket 0 = empty), descending.
 __device__ __forceinline__ uint32_t tile_len(const RasterArgs& a, uint32_t t) {
-  const uint64_t s0 = a.ws.tstart[t] < a.cap ? a.ws.tstart[t] : a.cap;
-  const uint64_t s1 = a.ws.tstart[t + 1] < a.cap ? a.ws.tstart[t + 1] : a.cap;
+  const uint64_t s0 = tile_begin(a, t);
+  const uint64_t s1 = tile_begin(a, t + 1);
   return uint32_t(s1 - s0);
 }
 
@@ -399,7 +401,9 @@ hipError_t launch_order(const RasterArgs& a, hipStream_t s) {
 // LDS; longer lists are sorted in kSortCap runs and merged pairwise (each key
 // finds its rank in the partner run by binary search) until one run remains.
 // Keys are unique for non-overlapping leaves, so the order is deterministic.
-constexpr int kSortThreads = 256;
+// One wave per tile: most lists are a few hundred keys, and a single-wave
+// workgroup synchronises its bitonic stages without cross-wave barriers.
+constexpr int kSortThreads = 64;
 
 __device__ void lds_bitonic(unsigned long long* sk, uint32_t npow) {
   for (uint32_t k = 2; k <= npow; k <<= 1) {
@@ -430,8 +434,8 @@ __device__ void sort_run(unsigned long long* sk, const unsigned long long* src,
 __global__ __launch_bounds__(kSortThreads) void k_sort(RasterArgs a) {
   __shared__ unsigned long long sk[kSortCap];
   const uint32_t t = blockIdx.x;
-  const uint64_t s0 = a.ws.tstart[t] < a.cap ? a.ws.tstart[t] : a.cap;
-  const uint64_t s1 = a.ws.tstart[t + 1] < a.cap ? a.ws.tstart[t + 1] : a.cap;
+  const uint64_t s0 = tile_begin(a, t);
+  const uint64_t s1 = tile_begin(a, t + 1);
   const uint32_t n = uint32_t(s1 - s0);
   if (n == 0) return;
   unsigned long long* keys = a.ws.pairs + s0;

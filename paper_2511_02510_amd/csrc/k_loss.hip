@@ -16,47 +16,12 @@ struct LossWS {
   uint32_t* hist;    // [V][256]
   SelState* st;      // [V]
   double* sums;      // [V]
+  uint32_t* done;    // blocks finished in the current histogram pass
 };
-
-// One block per segment: pick the digit whose cumulative count passes k,
-// then clear the segment's histogram for the next pass.  256 threads.
-__global__ __launch_bounds__(256) void k_sel_step(SelState* st, uint32_t* hist, int pass) {
-  __shared__ uint32_t s_w[4];
-  SelState* S = st + blockIdx.x;
-  uint32_t* h = hist + size_t(blockIdx.x) * 256;
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const uint32_t c = h[t];
-  uint32_t x = c;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
-  }
-  if (lane == 63) s_w[w] = x;
-  __syncthreads();
-  uint32_t add = 0;
-  for (int q = 0; q < w; ++q) add += s_w[q];
-  const uint32_t incl = x + add;
-  const uint32_t excl = incl - c;
-  const uint32_t k = S->k;
-  const bool valid = S->valid != 0;
-  __syncthreads();
-  if (valid && c > 0 && excl <= k && k < incl) {
-    S->prefix = S->prefix | (uint32_t(t) << sel_shift(pass));
-    S->k = k - excl;
-  }
-  h[t] = 0u;
-}
-
-hipError_t launch_sel_step(SelState* st, uint32_t* hist, int nseg, int pass, hipStream_t s) {
-  if (nseg <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_sel_step, dim3(nseg), dim3(256), 0, s, st, hist, pass);
-  return hipGetLastError();
-}
 
 uint64_t loss_ws_bytes(int V) {
   return align256(size_t(V) * 256 * 4) + align256(size_t(V) * sizeof(SelState)) +
-         align256(size_t(V) * 8);
+         align256(size_t(V) * 8) + 256;
 }
 
 static LossWS loss_bind(void* base, int V) {
@@ -67,6 +32,8 @@ static LossWS loss_bind(void* base, int V) {
   w.st = reinterpret_cast<SelState*>(b);
   b += align256(size_t(V) * sizeof(SelState));
   w.sums = reinterpret_cast<double*>(b);
+  b += align256(size_t(V) * 8);
+  w.done = reinterpret_cast<uint32_t*>(b);
   return w;
 }
 
@@ -89,6 +56,7 @@ __global__ void k_loss_setup(const lv_camera* cams, int V, LossWS w, double q) {
     w.st[v].n = uint32_t(P);
     w.st[v].valid = P > 0 ? 1u : 0u;
     w.sums[v] = 0.0;
+    if (v == 0) *w.done = 0u;
   }
 }
 
@@ -137,6 +105,7 @@ __global__ __launch_bounds__(256) void k_hist_views(const lv_camera* cams, const
   __syncthreads();
   const uint32_t c = lh[threadIdx.x];
   if (c) atomicAdd(&w.hist[size_t(v) * 256 + threadIdx.x], c);
+  sel_finish_pass(w.st, w.hist, gridDim.y, pass, w.done);
 }
 
 __global__ __launch_bounds__(256) void k_lf_weight(const lv_camera* cams, float* wbuf, LossWS w,
@@ -189,10 +158,8 @@ hipError_t run_lf_weight(const lv_camera* cams_dev, int V, uint64_t max_pix, con
   const dim3 grid(blocks_for(max_pix), V);
   hipLaunchKernelGGL(k_loss_setup, dim3(V), dim3(256), 0, s, cams_dev, V, w, 0.99);
   hipLaunchKernelGGL(k_sobel, grid, dim3(256), 0, s, cams_dev, target, weight);
-  for (int pass = 0; pass < 4; ++pass) {
+  for (int pass = 0; pass < 4; ++pass)
     hipLaunchKernelGGL(k_hist_views, grid, dim3(256), 0, s, cams_dev, (const float*)weight, w, pass);
-    launch_sel_step(w.st, w.hist, V, pass, s);
-  }
   hipLaunchKernelGGL(k_lf_weight, grid, dim3(256), 0, s, cams_dev, weight, w, gamma, form, eps);
   hipLaunchKernelGGL(k_lf_norm, grid, dim3(256), 0, s, cams_dev, weight, w);
   return hipGetLastError();

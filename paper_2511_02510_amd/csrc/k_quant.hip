@@ -7,8 +7,8 @@
 //   3. z~ = clip((delta - p5) / (p95 - p5), 0, 1), bin = min(B-1, floor(B z~));
 //   4. tau_b = ceil(q |V_b|)-th smallest w_max of bin b (the generalised
 //      inverse of the bin's empirical CDF), prune = w_max <= tau_bin.
-// All selections are exact radix selects on device; nothing returns to the
-// host.
+// All selections are exact radix selects on device (p5 and p95 in the same
+// passes); nothing returns to the host.
 #include "lv_common.h"
 #include "lv_select.h"
 
@@ -21,11 +21,12 @@ struct QuantWS {
   uint32_t* hist;     // [2 + B][256]
   SelState* st;       // [2 + B]: p5, p95, bins
   uint32_t* cnt;      // [B]
+  uint32_t* done;     // blocks finished in the current pass
 };
 
 uint64_t quant_ws_bytes(int64_t n, int B) {
   return align256(4 * size_t(n)) * 2 + align256(size_t(n)) + align256(size_t(2 + B) * 1024) +
-         align256(size_t(2 + B) * sizeof(SelState)) + align256(4 * size_t(B));
+         align256(size_t(2 + B) * sizeof(SelState)) + align256(4 * size_t(B)) + 256;
 }
 
 static QuantWS quant_bind(void* base, int64_t n, int B) {
@@ -36,7 +37,8 @@ static QuantWS quant_bind(void* base, int64_t n, int B) {
   w.bins = reinterpret_cast<uint8_t*>(b); b += align256(size_t(n));
   w.hist = reinterpret_cast<uint32_t*>(b); b += align256(size_t(2 + B) * 1024);
   w.st = reinterpret_cast<SelState*>(b); b += align256(size_t(2 + B) * sizeof(SelState));
-  w.cnt = reinterpret_cast<uint32_t*>(b);
+  w.cnt = reinterpret_cast<uint32_t*>(b); b += align256(4 * size_t(B));
+  w.done = reinterpret_cast<uint32_t*>(b);
   return w;
 }
 
@@ -56,6 +58,7 @@ __global__ void k_q_setup(QuantWS w, int B, uint32_t n) {
     w.st[s].valid = (s < 2 && n > 0) ? 1u : 0u;
     w.st[s].k = s == 0 ? rank_of(0.05, n) : (s == 1 ? rank_of(0.95, n) : 0u);
     if (s >= 2) w.cnt[s - 2] = 0u;
+    if (s == 0) *w.done = 0u;
   }
 }
 
@@ -81,29 +84,41 @@ __global__ __launch_bounds__(256) void k_q_delta(RasterArgs a, QuantWS w) {
   w.wkey[i] = f2key(a.wmax[i]);
 }
 
-// histogram of the current digit; segment = label (nullptr: segment seg0)
+// Histogram of the current digit.  dual: every element counts towards
+// segments seg0 and seg0 + 1 (p5 and p95 of the same keys); otherwise the
+// element's segment is seg0 + label (label 0 when labels is null).
 __global__ __launch_bounds__(256) void k_q_hist(const uint32_t* keys, const uint8_t* labels, int64_t n,
-                                                QuantWS w, int seg0, int nseg, int pass) {
+                                                QuantWS w, int seg0, int nseg, int pass, int dual) {
   extern __shared__ uint32_t lh[];
   for (int k = threadIdx.x; k < nseg * 256; k += 256) lh[k] = 0u;
   __syncthreads();
   const int sh = sel_shift(pass);
   const uint32_t hm = sel_himask(pass);
+  const SelState* st = w.st + seg0;
   for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
-    const int s = labels ? int(labels[i]) : 0;
-    const SelState& st = w.st[seg0 + s];
     const uint32_t key = keys[i];
-    if (st.valid && (key & hm) == st.prefix) atomicAdd(&lh[s * 256 + ((key >> sh) & 255u)], 1u);
+    const uint32_t d = (key >> sh) & 255u;
+    if (dual) {
+      if (st[0].valid && (key & hm) == st[0].prefix) atomicAdd(&lh[d], 1u);
+      if (st[1].valid && (key & hm) == st[1].prefix) atomicAdd(&lh[256 + d], 1u);
+    } else {
+      const int s = labels ? int(labels[i]) : 0;
+      if (st[s].valid && (key & hm) == st[s].prefix) atomicAdd(&lh[s * 256 + d], 1u);
+    }
   }
   __syncthreads();
   for (int k = threadIdx.x; k < nseg * 256; k += 256) {
     const uint32_t c = lh[k];
     if (c) atomicAdd(&w.hist[size_t(seg0) * 256 + k], c);
   }
+  sel_finish_pass(w.st + seg0, w.hist + size_t(seg0) * 256, nseg, pass, w.done);
 }
 
-__global__ __launch_bounds__(256) void k_q_bins(int64_t n, int B, QuantWS w, uint8_t* out_bins) {
+// bins from delta and (p5, p95); the last block turns the bin counts into the
+// per-bin selection ranks
+__global__ __launch_bounds__(256) void k_q_bins(int64_t n, int B, double q, QuantWS w, uint8_t* out_bins) {
   extern __shared__ uint32_t lc[];
+  __shared__ uint32_t s_last;
   for (int k = threadIdx.x; k < B; k += 256) lc[k] = 0u;
   __syncthreads();
   const float p5 = key2f(w.st[0].prefix), p95 = key2f(w.st[1].prefix);
@@ -129,17 +144,22 @@ __global__ __launch_bounds__(256) void k_q_bins(int64_t n, int B, QuantWS w, uin
   __syncthreads();
   for (int k = threadIdx.x; k < B; k += 256)
     if (lc[k]) atomicAdd(&w.cnt[k], lc[k]);
-}
-
-__global__ void k_q_rank(QuantWS w, int B, double q) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= B) return;
-  const uint32_t c = w.cnt[b];
-  SelState& st = w.st[2 + b];
-  st.prefix = 0u;
-  st.n = c;
-  st.valid = c > 0 ? 1u : 0u;
-  st.k = c > 0 ? rank_of(q, c) : 0u;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) s_last = (atomicAdd(w.done, 1u) == gridDim.x - 1u) ? 1u : 0u;
+  __syncthreads();
+  if (s_last) {
+    __threadfence();
+    for (int b = threadIdx.x; b < B; b += 256) {
+      const uint32_t c = __hip_atomic_load(&w.cnt[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      SelState& st = w.st[2 + b];
+      st.prefix = 0u;
+      st.n = c;
+      st.valid = c > 0 ? 1u : 0u;
+      st.k = c > 0 ? rank_of(q, c) : 0u;
+    }
+    if (threadIdx.x == 0) *w.done = 0u;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_q_prune(int64_t n, int B, QuantWS w, const float* wmax,
@@ -170,22 +190,14 @@ hipError_t run_depth_quantile(const RasterArgs& a, int B, double q, void* ws, fl
   if (a.n > 0) {
     hipLaunchKernelGGL(k_q_delta, dim3(uint32_t((a.n + 255) / 256)), dim3(256), 0, s, a, w);
     const uint32_t g = grid_for(a.n);
-    // p5 and p95 of delta (segments 0 and 1, every voxel in each)
-    for (int seg = 0; seg < 2; ++seg)
-      for (int pass = 0; pass < 4; ++pass) {
-        hipLaunchKernelGGL(k_q_hist, dim3(g), dim3(256), 256 * 4, s, (const uint32_t*)w.dkey,
-                           (const uint8_t*)nullptr, a.n, w, seg, 1, pass);
-        launch_sel_step(w.st + seg, w.hist + size_t(seg) * 256, 1, pass, s);
-      }
-    hipLaunchKernelGGL(k_q_bins, dim3(g), dim3(256), B * 4, s, a.n, B, w, out_bins);
-    hipLaunchKernelGGL(k_q_rank, dim3((B + 63) / 64), dim3(64), 0, s, w, B, q);
-    for (int pass = 0; pass < 4; ++pass) {
+    // p5 and p95 of delta: segments 0 and 1 over every voxel, in the same passes
+    for (int pass = 0; pass < 4; ++pass)
+      hipLaunchKernelGGL(k_q_hist, dim3(g), dim3(256), 2 * 256 * 4, s, (const uint32_t*)w.dkey,
+                         (const uint8_t*)nullptr, a.n, w, 0, 2, pass, 1);
+    hipLaunchKernelGGL(k_q_bins, dim3(g), dim3(256), B * 4, s, a.n, B, q, w, out_bins);
+    for (int pass = 0; pass < 4; ++pass)
       hipLaunchKernelGGL(k_q_hist, dim3(g), dim3(256), size_t(B) * 256 * 4, s,
-                         (const uint32_t*)w.wkey, (const uint8_t*)w.bins, a.n, w, 2, B, pass);
-      launch_sel_step(w.st + 2, w.hist + 2 * 256, B, pass, s);
-    }
-  } else {
-    hipLaunchKernelGGL(k_q_rank, dim3((B + 63) / 64), dim3(64), 0, s, w, B, q);
+                         (const uint32_t*)w.wkey, (const uint8_t*)w.bins, a.n, w, 2, B, pass, 0);
   }
   hipLaunchKernelGGL(k_q_prune, dim3(uint32_t((a.n + 255) / 256) > 0 ? uint32_t((a.n + 255) / 256) : 1u),
                      dim3(256), 0, s, a.n, B, w, a.wmax, tau, prune);

@@ -109,34 +109,39 @@ __device__ __forceinline__ void stage_chunk(Stage<CH>& S, const RasterArgs& a, c
   }
 }
 
-// bits r of an 8-bit row (or column) mask covered by [lo, hi] relative to org
-__device__ __forceinline__ uint32_t span_bits(uint32_t range, int org) {
-  const int lo = int(range & 0xFFFFu) - org;
-  const int hi = int(range >> 16) - org;
-  const int l = lo < 0 ? 0 : lo;
-  const int h = hi > 7 ? 7 : hi;
-  if (l > h) return 0u;
-  return ((2u << h) - 1u) & ~((1u << l) - 1u);
-}
+// Coverage masks of a staged chunk, built once per tile: for every 64-voxel
+// word w and every tile row r (column c), a 64-bit mask of the voxels whose
+// pixel-centre range covers that row (column).  The waves share the 2 TS
+// ballots per word; a lane's candidate set is rows[w][its row] &
+// cols[w][its column].  Needs a barrier before the masks are read.
+template <int TS, int CH>
+struct Masks {
+  unsigned long long rows[CH / 64][TS];
+  unsigned long long cols[CH / 64][TS];
+};
 
-// Candidate mask of this lane for voxels [64 w, 64 w + 64) of the chunk: one
-// 64-bit ballot per pixel row and per pixel column of the wave's 8 x 8 block,
-// AND-ed for the lane's own row and column.
-template <int CH>
-__device__ __forceinline__ unsigned long long lane_mask(const Stage<CH>& S, int w, int bx, int by,
-                                                        int lx, int ly) {
-  const int j = w * 64 + (threadIdx.x & 63);
-  const uint32_t rb = span_bits(S.yr[j], by);
-  const uint32_t cbits = span_bits(S.xr[j], bx);
-  unsigned long long myr = 0, myc = 0;
+template <int TS, int CH>
+__device__ __forceinline__ void build_masks(const Stage<CH>& S, Masks<TS, CH>& M, uint32_t nc,
+                                            int tox, int toy) {
+  constexpr int NWAVES = TS * TS / 64;
+  constexpr int RPW = TS / NWAVES;   // rows (and columns) per wave
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nwords = int((nc + 63) / 64);
+  for (int w = 0; w < nwords; ++w) {
+    const int j = w * 64 + lane;
+    const int ylo = int(S.yr[j] & 0xFFFFu) - toy, yhi = int(S.yr[j] >> 16) - toy;
+    const int xlo = int(S.xr[j] & 0xFFFFu) - tox, xhi = int(S.xr[j] >> 16) - tox;
 #pragma unroll
-  for (int r = 0; r < 8; ++r) {
-    const unsigned long long br = __ballot((rb >> r) & 1u);
-    const unsigned long long bc = __ballot((cbits >> r) & 1u);
-    myr = (ly == r) ? br : myr;
-    myc = (lx == r) ? bc : myc;
+    for (int k = 0; k < RPW; ++k) {
+      const int r = wave * RPW + k;
+      const unsigned long long br = __ballot(r >= ylo && r <= yhi);
+      const unsigned long long bc = __ballot(r >= xlo && r <= xhi);
+      if (lane == k) {
+        M.rows[w][r] = br;
+        M.cols[w][r] = bc;
+      }
+    }
   }
-  return myr & myc;
 }
 
 struct Seg {
@@ -236,6 +241,7 @@ __global__ __launch_bounds__(TS* TS) void k_composite_fwd(RasterArgs a) {
   constexpr int CH = 64 * NW;
   constexpr int BPR = TS / 8;
   __shared__ Stage<CH> S;
+  __shared__ Masks<TS, CH> MK;
   __shared__ uint32_t s_wmax[CH];
   __shared__ uint32_t s_tile;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -259,8 +265,8 @@ __global__ __launch_bounds__(TS* TS) void k_composite_fwd(RasterArgs a) {
     const lv_camera& cam = a.cams[v];
     const float o[3] = {cam.o[0], cam.o[1], cam.o[2]};
     const Ray ray = pixel_ray(cam, px, py);
-    const uint64_t s0 = a.ws.tstart[gt] < a.cap ? a.ws.tstart[gt] : a.cap;
-    const uint64_t s1 = a.ws.tstart[gt + 1] < a.cap ? a.ws.tstart[gt + 1] : a.cap;
+    const uint64_t s0 = tile_begin(a, gt);
+    const uint64_t s1 = tile_begin(a, gt + 1);
     const uint32_t count = uint32_t(s1 - s0);
     const uint32_t* ids = a.ws.ids + s0;
 
@@ -272,10 +278,12 @@ __global__ __launch_bounds__(TS* TS) void k_composite_fwd(RasterArgs a) {
       stage_chunk<CH, NT>(S, a, ids, cb, nc, v, o);
       for (int k = threadIdx.x; k < CH; k += NT) s_wmax[k] = 0u;
       __syncthreads();
+      build_masks<TS, CH>(S, MK, nc, tx * TS, ty * TS);
+      __syncthreads();
 #pragma unroll 1
       for (int w = 0; w < NW; ++w) {
         if (uint32_t(w * 64) >= nc) break;
-        unsigned long long m = lane_mask(S, w, bx, by, lx, ly);
+        unsigned long long m = MK.rows[w][wby + ly] & MK.cols[w][wbx + lx];
         if (st.done) m = 0;
         while (m) {
           const int jj = w * 64 + __builtin_ctzll(m);
@@ -393,6 +401,7 @@ __global__ __launch_bounds__(TS* TS) void k_composite_bwd(RasterArgs a) {
   constexpr int BPR = TS / 8;
   constexpr int NC = AccCopies<CH>::value;
   __shared__ Stage<CH> S;
+  __shared__ Masks<TS, CH> MK;
   __shared__ float s_g[11][CH][NC];
   __shared__ uint32_t s_tile, s_maxn;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -420,7 +429,7 @@ __global__ __launch_bounds__(TS* TS) void k_composite_bwd(RasterArgs a) {
     const lv_camera& cam = a.cams[v];
     const float o[3] = {cam.o[0], cam.o[1], cam.o[2]};
     const Ray ray = pixel_ray(cam, px, py);
-    const uint64_t s0 = a.ws.tstart[gt] < a.cap ? a.ws.tstart[gt] : a.cap;
+    const uint64_t s0 = tile_begin(a, gt);
     const uint32_t* ids = a.ws.ids + s0;
 
     uint32_t nlast = 0;
@@ -454,10 +463,12 @@ __global__ __launch_bounds__(TS* TS) void k_composite_bwd(RasterArgs a) {
         for (int k = threadIdx.x; k < 11 * CH * NC; k += NT) z[k] = 0.0f;
       }
       __syncthreads();
+      build_masks<TS, CH>(S, MK, nc, tx * TS, ty * TS);
+      __syncthreads();
 #pragma unroll 1
       for (int w = NW - 1; w >= 0; --w) {
         if (uint32_t(w * 64) >= nc) continue;
-        unsigned long long m = lane_mask(S, w, bx, by, lx, ly);
+        unsigned long long m = MK.rows[w][wby + ly] & MK.cols[w][wbx + lx];
         const int lim = int(nlast) - int(cb) - w * 64;
         if (lim <= 0) m = 0;
         else if (lim < 64) m &= (1ull << lim) - 1ull;
@@ -475,21 +486,17 @@ __global__ __launch_bounds__(TS* TS) void k_composite_bwd(RasterArgs a) {
       __syncthreads();
       for (uint32_t k = threadIdx.x; k < nc; k += NT) {
         const uint32_t id = S.id[k];
-        float gs[11];
-#pragma unroll
+        float* dc = a.ws.dcol + (size_t(v) * size_t(a.n) + id) * 3;
+#pragma unroll 1
         for (int c = 0; c < 11; ++c) {
           float s = 0.0f;
 #pragma unroll
           for (int q = 0; q < NC; ++q) s += s_g[c][k][q];
-          gs[c] = s;
+          if (s != 0.0f) {
+            float* dst = c < 8 ? &a.d_density[size_t(c) * size_t(a.n) + id] : &dc[c - 8];
+            unsafeAtomicAdd(dst, s);
+          }
         }
-#pragma unroll
-        for (int c = 0; c < 8; ++c)
-          if (gs[c] != 0.0f) unsafeAtomicAdd(&a.d_density[size_t(c) * size_t(a.n) + id], gs[c]);
-        float* dc = a.ws.dcol + (size_t(v) * size_t(a.n) + id) * 3;
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch)
-          if (gs[8 + ch] != 0.0f) unsafeAtomicAdd(&dc[ch], gs[8 + ch]);
       }
       __syncthreads();
     }

@@ -269,7 +269,8 @@ lv_status lv_forward(lv_context* ctx, const lv_voxels* vox, const lv_frame* fram
   {
     PhaseTimer t(ctx, LV_PH_SETUP, stream);
     LV_TRY(lv::launch_setup(a, stream), "setup");
-    LV_TRY(lv::launch_fill_u32(a.ws.tcount, uint64_t(L.T) + 1, 0u, stream), "fill tile counts");
+    LV_TRY(lv::launch_fill_u32(a.ws.tcount, uint64_t(L.T) * lv::kSpread + 1, 0u, stream),
+           "fill tile counts");
   }
   {
     PhaseTimer t(ctx, LV_PH_PREPROCESS, stream);
@@ -363,8 +364,10 @@ lv_status lv_export_bins(lv_context* ctx, const lv_voxels* vox, const lv_frame* 
   if (!workspace) return fail(ctx, LV_ERR_ARG, "workspace is NULL");
   LV_TRY(hipStreamSynchronize(stream), "synchronize");
   const char* base = static_cast<const char*>(workspace);
+  std::vector<uint32_t> sub(size_t(L.T) * lv::kSpread + 1);
+  LV_TRY(hipMemcpy(sub.data(), base + L.off_tstart, 4 * sub.size(), hipMemcpyDeviceToHost), "tile_start");
   std::vector<uint32_t> ts(size_t(L.T) + 1);
-  LV_TRY(hipMemcpy(ts.data(), base + L.off_tstart, 4 * ts.size(), hipMemcpyDeviceToHost), "tile_start");
+  for (size_t t = 0; t <= L.T; ++t) ts[t] = sub[t * lv::kSpread];
   if (tile_start) std::memcpy(tile_start, ts.data(), 4 * ts.size());
   const uint64_t tot = std::min<uint64_t>(ts[L.T], L.cap);
   if (ids && tot) LV_TRY(hipMemcpy(ids, base + L.off_ids, 4 * tot, hipMemcpyDeviceToHost), "ids");

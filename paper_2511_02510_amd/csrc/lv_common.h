@@ -12,9 +12,15 @@ namespace lv {
 constexpr int kLMax = LV_MAX_LEVEL;   // visibility code: 3 bits per level, 36 bits
 constexpr int kIdBits = 28;           // voxel id bits in a sort key
 constexpr uint32_t kIdMask = (1u << kIdBits) - 1u;
-constexpr int kSortCap = 4096;        // longest tile list sorted in one LDS pass
+constexpr int kSortCap = 2048;        // longest tile list sorted in one LDS pass
 constexpr float kZNear = 1e-4f;       // binning near plane (camera-space z)
 constexpr int kCounterWords = 128;
+// Each tile has kSpread pair counters (chosen by voxel id & (kSpread - 1)),
+// stored sub-counter-major so that the atomics on one tile's counters fall on
+// different cache lines; the scan visits them tile-major, so every tile's
+// pairs still form one contiguous segment [tstart[t * kSpread],
+// tstart[(t + 1) * kSpread]).
+constexpr int kSpread = 16;
 
 // per-view table built on the device from the cameras (graph-replay safe)
 struct ViewTab {
@@ -92,20 +98,20 @@ inline bool make_layout(const lv_voxels* vox, const lv_frame* fr, const lv_setti
     T += tx * ty;
     P += uint64_t(c.width) * uint64_t(c.height);
   }
-  if (T >= (1ull << 31)) return false;
+  if (T * kSpread >= (1ull << 31)) return false;
   L.T = uint32_t(T);
   L.P = P;
   L.cap = st->pair_capacity;
-  L.nblk_scan = uint32_t((T + 1 + kScanBlock - 1) / kScanBlock);
+  L.nblk_scan = uint32_t((T * kSpread + 1 + kScanBlock - 1) / kScanBlock);
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
   L.off_views = take(sizeof(ViewTab) * size_t(L.V));
   L.off_counters = take(4 * kCounterWords);
   L.off_vox = take(sizeof(VoxRec) * size_t(L.n));
   L.off_rec = take(sizeof(Rec) * size_t(L.n) * size_t(L.V));
-  L.off_tcount = take(4 * size_t(L.T + 1));
-  L.off_tstart = take(4 * size_t(L.T + 1));
-  L.off_tfill = take(4 * size_t(L.T + 1));
+  L.off_tcount = take(4 * (size_t(L.T) * kSpread + 1));
+  L.off_tstart = take(4 * (size_t(L.T) * kSpread + 1));
+  L.off_tfill = take(4 * (size_t(L.T) * kSpread + 1));
   L.off_torder = take(4 * size_t(L.T + 1));
   L.off_bsum = take(8 * size_t(L.nblk_scan + 1));   // 64-bit block sums
   L.off_pairs = take(8 * size_t(L.cap));
@@ -193,6 +199,12 @@ struct RasterArgs {
 };
 
 // ---------------------------------------------------------------- helpers
+// first pair of tile t (tile t + 1's start is its end), clipped to capacity
+__device__ __forceinline__ uint64_t tile_begin(const RasterArgs& a, uint32_t t) {
+  const uint64_t s = a.ws.tstart[uint64_t(t) * kSpread];
+  return s < a.cap ? s : a.cap;
+}
+
 __device__ __forceinline__ int view_of_tile(const ViewTab* vt, int V, uint32_t gt) {
   int lo = 0, hi = V - 1;
   while (lo < hi) {
