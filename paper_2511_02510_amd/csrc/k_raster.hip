@@ -5,11 +5,10 @@
 // queue ordered longest list first.  A tile's front-to-back voxel list is
 // staged in LDS `chunk` voxels at a time (geometry relative to the camera,
 // trilinear density coefficients, colour, pixel-centre coverage).  Per 64
-// staged voxels each wave builds, with 16 ballots, one 64-bit mask per pixel
-// row and per pixel column of its block; a lane's candidate set is the AND of
-// its row and column masks, so it visits only voxels whose projected box
-// covers its pixel centre, in list order (lowest bit first; backward: highest
-// first).  A lane stops once its transmittance falls below t_eps; the wave
+// staged voxels the workgroup builds, with ballots, one 64-bit mask per tile
+// row and per tile column; a lane's candidate set is the AND of its row and
+// column masks, so it visits only voxels whose projected box covers its pixel
+// centre, in list order (lowest bit first; backward: highest first).  A lane stops once its transmittance falls below t_eps; the wave
 // and the workgroup stop when every lane has.
 //
 // Optical depth: the trilinear density along a chord is a cubic in t, so the
@@ -18,9 +17,10 @@
 // w_max (eq. 5) is max-reduced per chunk in LDS (integer max on the bits of a
 // non-negative float, exact and order-independent) and then flushed with one
 // global atomic max per (tile, voxel).  Backward gradients (8 corner
-// densities + 3 colour channels per voxel) are pre-reduced per chunk in LDS
-// (in lane-spread copies, see the backward kernel) and flushed with one global
-// atomic add per (tile, voxel, component).
+// densities + 3 colour channels per voxel) are first summed over runs of
+// lanes that hold the same voxel in the same step (DPP, each 16-lane row a
+// 4 x 4 pixel block), then pre-reduced per chunk in LDS and flushed with one
+// global atomic add per (tile, voxel, component).
 #include "lv_common.h"
 
 namespace lv {
@@ -198,13 +198,60 @@ __device__ __forceinline__ Quad quad(const Stage<CH>& S, int j, const Ray& ray, 
 }
 
 // alpha = 1 - exp(-tau) without cancellation for small tau
+// (both forms are evaluated and one is selected: lanes of a wave disagree)
 __device__ __forceinline__ float opacity(float tau, float ex) {
-  if (tau < kSmallTau) {
-    return tau * (1.0f - tau * (0.5f - tau * (0.16666667f - tau * 0.041666667f)));
-  }
-  return 1.0f - ex;
+  const float series = tau * (1.0f - tau * (0.5f - tau * (0.16666667f - tau * 0.041666667f)));
+  return tau < kSmallTau ? series : 1.0f - ex;
 }
 
+
+// ------------------------------------------------ run-combined LDS updates
+// Neighbouring pixels walk nearly the same voxel lists in lockstep, so in one
+// step many lanes of a wave update the same voxel, and LDS atomics on one
+// address are executed one lane at a time.  Each 16-lane DPP row covers a
+// 4 x 4 pixel block; runs of consecutive lanes of a row that hold the same
+// voxel are summed by a segmented inclusive scan (row shifts by 1, 2, 4, 8)
+// and only the last lane of a run updates LDS.  The LDS accumulators are
+// doubles: on gfx950 an LDS add on f64 costs about a tenth of one on f32 per
+// lane (and rounds less).  Must be called with every lane of the wave active.
+__device__ __forceinline__ int pix_x_of_lane(int lane) { return ((lane >> 4) & 1) * 4 + (lane & 3); }
+__device__ __forceinline__ int pix_y_of_lane(int lane) { return (lane >> 5) * 4 + ((lane >> 2) & 3); }
+
+template <int K>
+__device__ __forceinline__ float row_shr(float v) {   // lanes with no source read 0
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x110 + K, 0xF, 0xF, false));
+}
+
+template <int K, int NV>
+__device__ __forceinline__ void seg_step(float* v, int dist) {
+  if (__ballot(dist >= K) == 0) return;
+#pragma unroll
+  for (int c = 0; c < NV; ++c) {
+    const float t = row_shr<K>(v[c]);
+    v[c] = dist >= K ? v[c] + t : v[c];
+  }
+}
+
+// After the call, a lane with `last` set holds in v the sum over its run of
+// lanes with the same key (pend lanes only; others form runs of their own).
+template <int NV>
+__device__ __forceinline__ bool seg_reduce_rows(float* v, int jj, bool pend) {
+  const int lane = threadIdx.x & 63;
+  const int key = pend ? jj : -1 - lane;
+  const int prev = __builtin_amdgcn_update_dpp(0x7FFFFFFF, key, 0x111, 0xF, 0xF, false);
+  const bool head = (lane & 15) == 0 || prev != key;
+  const unsigned long long H = __ballot(head);
+  const bool last = (lane & 15) == 15 || (((H >> lane) >> 1) & 1ull);
+  if (H != ~0ull) {
+    const unsigned long long le = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+    const int dist = lane - (63 - __builtin_clzll(H & le));
+    seg_step<1, NV>(v, dist);
+    seg_step<2, NV>(v, dist);
+    seg_step<4, NV>(v, dist);
+    seg_step<8, NV>(v, dist);
+  }
+  return last;
+}
 
 // ======================================================================
 // forward
@@ -248,8 +295,15 @@ __global__ __launch_bounds__(TS* TS) void k_composite_fwd(RasterArgs a) {
   const int lx = lane & 7, ly = lane >> 3;
   const int wbx = (wave % BPR) * 8, wby = (wave / BPR) * 8;
 
+  // the next queue slot is taken while the current tile is processed; a
+  // block stops at the first slot past the end (every later one is too)
+  uint32_t next = 0;
+  if (threadIdx.x == 0) next = atomicAdd(&a.ws.counters[C_QFWD], 1u);
   for (;;) {
-    if (threadIdx.x == 0) s_tile = atomicAdd(&a.ws.counters[C_QFWD], 1u);
+    if (threadIdx.x == 0) {
+      s_tile = next;
+      next = atomicAdd(&a.ws.counters[C_QFWD], 1u);
+    }
     __syncthreads();
     const uint32_t qi = s_tile;
     __syncthreads();
@@ -325,11 +379,10 @@ __global__ __launch_bounds__(TS* TS) void k_composite_fwd(RasterArgs a) {
 // T_{k-1} = T_k exp(tau_k), starting from the transmittance saved before the
 // last hit, so no per-sample state is stored.
 //
-// Accumulation: the 11 contributions of a fragment are added with LDS atomics
-// into one of NC copies of the voxel's accumulator, chosen by lane & (NC-1),
-// so that the many lanes covered by one large voxel do not all serialise on
-// the same LDS address; the copies are summed when the chunk is flushed to
-// global memory.
+// Accumulation: the 11 contributions of a fragment are summed over runs of
+// lanes on the same voxel (seg_reduce_rows), added to the voxel's LDS
+// accumulator by the run's last lane, and each chunk is flushed with one
+// global atomic per (voxel, component).
 struct BwdState {
   float Tb;            // transmittance before the hit processed last
   float gC0, gC1, gC2, gD, gA;
@@ -390,29 +443,26 @@ __device__ __forceinline__ bool bwd_fragment(const Stage<CH>& S, int jj, const R
   return true;
 }
 
-// copies of each voxel accumulator: LDS for the accumulators stays ~22 KB
-template <int CH>
-struct AccCopies { static constexpr int value = CH <= 64 ? 8 : (CH <= 128 ? 4 : 2); };
-
 template <int TS, int NW>
 __global__ __launch_bounds__(TS* TS) void k_composite_bwd(RasterArgs a) {
   constexpr int NT = TS * TS;
   constexpr int CH = 64 * NW;
   constexpr int BPR = TS / 8;
-  constexpr int NC = AccCopies<CH>::value;
   __shared__ Stage<CH> S;
   __shared__ Masks<TS, CH> MK;
-  __shared__ float s_g[11][CH][NC];
+  __shared__ double s_g[11][CH];
   __shared__ uint32_t s_tile, s_maxn;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int lx = lane & 7, ly = lane >> 3;
-  const int copy = lane & (NC - 1);
+  const int lx = pix_x_of_lane(lane), ly = pix_y_of_lane(lane);
   const int wbx = (wave % BPR) * 8, wby = (wave / BPR) * 8;
   const float bg[3] = {a.bg[0], a.bg[1], a.bg[2]};
 
+  uint32_t next = 0;
+  if (threadIdx.x == 0) next = atomicAdd(&a.ws.counters[C_QBWD], 1u);
   for (;;) {
     if (threadIdx.x == 0) {
-      s_tile = atomicAdd(&a.ws.counters[C_QBWD], 1u);
+      s_tile = next;
+      next = atomicAdd(&a.ws.counters[C_QBWD], 1u);
       s_maxn = 0u;
     }
     __syncthreads();
@@ -459,8 +509,8 @@ __global__ __launch_bounds__(TS* TS) void k_composite_bwd(RasterArgs a) {
       const uint32_t nc = (maxn - cb) < uint32_t(CH) ? (maxn - cb) : uint32_t(CH);
       stage_chunk<CH, NT>(S, a, ids, cb, nc, v, o);
       {
-        float* z = &s_g[0][0][0];
-        for (int k = threadIdx.x; k < 11 * CH * NC; k += NT) z[k] = 0.0f;
+        double* z = &s_g[0][0];
+        for (int k = threadIdx.x; k < 11 * CH; k += NT) z[k] = 0.0;
       }
       __syncthreads();
       build_masks<TS, CH>(S, MK, nc, tx * TS, ty * TS);
@@ -472,30 +522,39 @@ __global__ __launch_bounds__(TS* TS) void k_composite_bwd(RasterArgs a) {
         const int lim = int(nlast) - int(cb) - w * 64;
         if (lim <= 0) m = 0;
         else if (lim < 64) m &= (1ull << lim) - 1ull;
-        while (m) {
-          const int jbit = 63 - __builtin_clzll(m);
-          m &= ~(1ull << jbit);
-          const int jj = w * 64 + jbit;
+        // wave-uniform loop: each lane takes its next candidate (back to front)
+        for (;;) {
+          const bool act = m != 0;
+          if (__ballot(act) == 0) break;
+          int jj = -1;
+          bool hit = false;
           float g[11];
-          if (bwd_fragment(S, jj, ray, st, bg, g)) {
 #pragma unroll
-            for (int c = 0; c < 11; ++c) atomicAdd(&s_g[c][jj][copy], g[c]);
+          for (int c = 0; c < 11; ++c) g[c] = 0.0f;
+          if (act) {
+            const int jbit = 63 - __builtin_clzll(m);
+            m &= ~(1ull << jbit);
+            jj = w * 64 + jbit;
+            hit = bwd_fragment(S, jj, ray, st, bg, g);
+          }
+          const bool last = seg_reduce_rows<11>(g, jj, hit);
+          if (hit && last) {
+#pragma unroll
+            for (int c = 0; c < 11; ++c) atomicAdd(&s_g[c][jj], double(g[c]));
           }
         }
       }
       __syncthreads();
-      for (uint32_t k = threadIdx.x; k < nc; k += NT) {
-        const uint32_t id = S.id[k];
-        float* dc = a.ws.dcol + (size_t(v) * size_t(a.n) + id) * 3;
-#pragma unroll 1
-        for (int c = 0; c < 11; ++c) {
-          float s = 0.0f;
-#pragma unroll
-          for (int q = 0; q < NC; ++q) s += s_g[c][k][q];
-          if (s != 0.0f) {
-            float* dst = c < 8 ? &a.d_density[size_t(c) * size_t(a.n) + id] : &dc[c - 8];
-            unsafeAtomicAdd(dst, s);
-          }
+      // flush: consecutive lanes take consecutive components of a voxel, so
+      // its 8 density and 3 colour sums go out as two contiguous groups
+      for (uint32_t e = threadIdx.x; e < 11u * nc; e += NT) {
+        const uint32_t k = e / 11u, c = e - 11u * k;
+        const float s = float(s_g[c][k]);
+        if (s != 0.0f) {
+          const size_t id = S.id[k];
+          float* dst = c < 8u ? &a.ws.dden[8 * id + c]
+                              : &a.ws.dcol[(size_t(v) * size_t(a.n) + id) * 3 + (c - 8u)];
+          unsafeAtomicAdd(dst, s);
         }
       }
       __syncthreads();
@@ -508,7 +567,7 @@ template <typename K>
 static int persistent_grid(K kernel, int nt, uint32_t T, int grid_cap) {
   int dev = 0, cus = 256, per = 1;
   if (hipGetDevice(&dev) == hipSuccess) {
-    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
   }
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, nt, 0) != hipSuccess || per < 1) per = 1;
   long g = long(cus) * per;

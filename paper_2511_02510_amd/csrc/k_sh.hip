@@ -1,13 +1,15 @@
 // Backward tail: colour gradients of every (view, voxel) record are taken
 // through the clamp at zero and the SH expansion to the SH coefficients,
-// summed over views.  One thread per voxel; the output rows are written
-// coalesced ([3 (deg+1)^2][n]) and fully overwritten.
+// summed over views, and the voxel-major corner-density gradient the
+// composite pass accumulated is transposed into the caller's [8][n] rows.
+// One thread per voxel; the output rows are written coalesced and fully
+// overwritten.
 #include "lv_common.h"
 
 namespace lv {
 
 hipError_t launch_bwd_setup(const RasterArgs& a, hipStream_t s) {
-  hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(a.d_density), 8ull * uint64_t(a.n), 0u, s);
+  hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(a.ws.dden), 8ull * uint64_t(a.n), 0u, s);
   if (e != hipSuccess) return e;
   e = launch_fill_u32(reinterpret_cast<uint32_t*>(a.ws.dcol), 3ull * uint64_t(a.n) * uint64_t(a.V), 0u, s);
   if (e != hipSuccess) return e;
@@ -20,6 +22,13 @@ __global__ __launch_bounds__(256) void k_sh_bwd(RasterArgs a) {
   const int64_t n = a.n;
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  {
+    const float4 d0 = reinterpret_cast<const float4*>(a.ws.dden)[2 * i];
+    const float4 d1 = reinterpret_cast<const float4*>(a.ws.dden)[2 * i + 1];
+    const float dd[8] = {d0.x, d0.y, d0.z, d0.w, d1.x, d1.y, d1.z, d1.w};
+#pragma unroll
+    for (int c = 0; c < 8; ++c) a.d_density[size_t(c) * size_t(n) + size_t(i)] = dd[c];
+  }
   float acc[NB][3];
 #pragma unroll
   for (int j = 0; j < NB; ++j) acc[j][0] = acc[j][1] = acc[j][2] = 0.0f;

@@ -78,15 +78,11 @@ struct PhaseTimer {
     if (c && c->timing && !c->capturing) {
       a = c->event();
       b = c->event();
-      if (a && b) hipEventRecord(a, s);
-      else a = b = nullptr;
+      if (!(a && b && hipEventRecord(a, s) == hipSuccess)) a = b = nullptr;
     }
   }
   ~PhaseTimer() {
-    if (a) {
-      hipEventRecord(b, s);
-      c->pending.push_back({ph, a, b});
-    }
+    if (a && hipEventRecord(b, s) == hipSuccess) c->pending.push_back({ph, a, b});
   }
 };
 
@@ -229,10 +225,10 @@ lv_status lv_create(lv_context** out, int hip_device) {
 
 void lv_destroy(lv_context* ctx) {
   if (!ctx) return;
-  if (ctx->exec) hipGraphExecDestroy(ctx->exec);
-  if (ctx->graph) hipGraphDestroy(ctx->graph);
-  for (auto& p : ctx->pending) { hipEventDestroy(p.a); hipEventDestroy(p.b); }
-  for (auto e : ctx->pool) hipEventDestroy(e);
+  if (ctx->exec) (void)hipGraphExecDestroy(ctx->exec);
+  if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+  for (auto& p : ctx->pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
+  for (auto e : ctx->pool) (void)hipEventDestroy(e);
   delete ctx;
 }
 
@@ -472,8 +468,8 @@ lv_status lv_graph_end(lv_context* ctx, hipStream_t stream) {
   ctx->capturing = false;
   hipGraph_t g = nullptr;
   LV_TRY(hipStreamEndCapture(stream, &g), "end capture");
-  if (ctx->exec) { hipGraphExecDestroy(ctx->exec); ctx->exec = nullptr; }
-  if (ctx->graph) { hipGraphDestroy(ctx->graph); ctx->graph = nullptr; }
+  if (ctx->exec) { (void)hipGraphExecDestroy(ctx->exec); ctx->exec = nullptr; }
+  if (ctx->graph) { (void)hipGraphDestroy(ctx->graph); ctx->graph = nullptr; }
   ctx->graph = g;
   LV_TRY(hipGraphInstantiate(&ctx->exec, g, nullptr, nullptr, 0), "instantiate graph");
   return LV_OK;
@@ -488,8 +484,8 @@ lv_status lv_graph_launch(lv_context* ctx, hipStream_t stream) {
 
 lv_status lv_graph_reset(lv_context* ctx) {
   if (!ctx) return LV_ERR_ARG;
-  if (ctx->exec) { hipGraphExecDestroy(ctx->exec); ctx->exec = nullptr; }
-  if (ctx->graph) { hipGraphDestroy(ctx->graph); ctx->graph = nullptr; }
+  if (ctx->exec) { (void)hipGraphExecDestroy(ctx->exec); ctx->exec = nullptr; }
+  if (ctx->graph) { (void)hipGraphDestroy(ctx->graph); ctx->graph = nullptr; }
   return LV_OK;
 }
 
@@ -544,10 +540,12 @@ lv_status lv_autotune(lv_context* ctx, const lv_voxels* vox, const lv_frame* fra
   lv_status result = LV_OK;
   float best_ms = -1.0f;
   auto cleanup = [&]() {
-    hipFree(rgb); hipFree(depth); hipFree(alpha); hipFree(wmax); hipFree(drgb);
-    hipFree(dd); hipFree(dsh); hipFree(ws);
-    if (e0) hipEventDestroy(e0);
-    if (e1) hipEventDestroy(e1);
+    for (void* p : {static_cast<void*>(rgb), static_cast<void*>(depth), static_cast<void*>(alpha),
+                    static_cast<void*>(wmax), static_cast<void*>(drgb), static_cast<void*>(dd),
+                    static_cast<void*>(dsh), ws})
+      if (p) (void)hipFree(p);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
   };
   bool ok = hipMalloc(&rgb, 12 * P) == hipSuccess && hipMalloc(&depth, 4 * P) == hipSuccess &&
             hipMalloc(&alpha, 4 * P) == hipSuccess && hipMalloc(&drgb, 12 * P) == hipSuccess &&
@@ -557,8 +555,11 @@ lv_status lv_autotune(lv_context* ctx, const lv_voxels* vox, const lv_frame* fra
             hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
   if (!ok) { cleanup(); return fail(ctx, LV_ERR_HIP, "autotune: allocation failed"); }
   // a small non-zero upstream gradient so the backward does its full work
-  lv::launch_fill_u32(reinterpret_cast<uint32_t*>(drgb), 3 * P, 0x358637bdu /* 1e-6f */, stream);
-  lv::launch_fill_u32(reinterpret_cast<uint32_t*>(wmax), uint64_t(n > 0 ? n : 1), 0u, stream);
+  if (lv::launch_fill_u32(reinterpret_cast<uint32_t*>(drgb), 3 * P, 0x358637bdu /* 1e-6f */, stream) != hipSuccess ||
+      lv::launch_fill_u32(reinterpret_cast<uint32_t*>(wmax), uint64_t(n > 0 ? n : 1), 0u, stream) != hipSuccess) {
+    cleanup();
+    return fail(ctx, LV_ERR_HIP, "autotune: fill failed");
+  }
   const bool was_timing = ctx->timing;
   ctx->timing = false;
   for (int ti = 0; ti < 3 && result == LV_OK; ++ti) {
@@ -572,7 +573,7 @@ lv_status lv_autotune(lv_context* ctx, const lv_voxels* vox, const lv_frame* fra
       lv::Layout L;
       validate_all(ctx, vox, frame, &st, &L);
       if (L.total > ws_bytes) {
-        hipFree(ws);
+        if (ws) (void)hipFree(ws);
         ws = nullptr;
         if (hipMalloc(&ws, L.total) != hipSuccess) { result = fail(ctx, LV_ERR_HIP, "autotune: workspace"); break; }
         ws_bytes = L.total;
@@ -590,13 +591,12 @@ lv_status lv_autotune(lv_context* ctx, const lv_voxels* vox, const lv_frame* fra
       // warm-up, then timed repetitions of forward + backward
       bool run_ok = true;
       for (int r = -1; r < reps && run_ok; ++r) {
-        if (r == 0) hipEventRecord(e0, stream);
+        if (r == 0 && hipEventRecord(e0, stream) != hipSuccess) { run_ok = false; break; }
         run_ok = lv_forward(ctx, vox, frame, &st, ws, rgb, depth, alpha, wmax, stream) == LV_OK &&
                  lv_backward(ctx, vox, frame, &st, ws, drgb, nullptr, nullptr, dd, dsh, stream) == LV_OK;
       }
-      hipEventRecord(e1, stream);
-      if (hipEventSynchronize(e1) != hipSuccess) run_ok = false;
-      if (run_ok) hipEventElapsedTime(&ms, e0, e1);
+      if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) run_ok = false;
+      if (run_ok && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) run_ok = false;
       ms = run_ok ? ms / reps : -1.0f;
       if (ms_table) ms_table[ti * 3 + ci] = ms;
       if (run_ok && (best_ms < 0.0f || ms < best_ms)) {

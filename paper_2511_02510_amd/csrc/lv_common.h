@@ -75,7 +75,7 @@ struct Layout {
   uint32_t nblk_scan = 0;  // blocks of the tile scan
   size_t off_views = 0, off_counters = 0, off_vox = 0, off_rec = 0, off_tcount = 0,
          off_tstart = 0, off_tfill = 0, off_torder = 0, off_bsum = 0, off_pairs = 0,
-         off_ids = 0, off_mtmp = 0, off_nlast = 0, off_tpre = 0, off_dcol = 0;
+         off_ids = 0, off_mtmp = 0, off_nlast = 0, off_tpre = 0, off_dcol = 0, off_dden = 0;
   size_t total = 0;
 };
 
@@ -120,6 +120,7 @@ inline bool make_layout(const lv_voxels* vox, const lv_frame* fr, const lv_setti
   L.off_nlast = take(4 * size_t(L.P));
   L.off_tpre = take(4 * size_t(L.P));
   L.off_dcol = take(12 * size_t(L.n) * size_t(L.V));
+  L.off_dden = take(32 * size_t(L.n));
   L.total = o;
   return true;
 }
@@ -140,7 +141,8 @@ struct WS {
   unsigned long long* mtmp;
   uint32_t* nlast;
   float* tpre;
-  float* dcol;
+  float* dcol;   // [V][n][3] colour gradient per (view, voxel)
+  float* dden;   // [n][8] corner-density gradient, voxel-major
 };
 
 inline WS bind(const Layout& L, void* base) {
@@ -161,6 +163,7 @@ inline WS bind(const Layout& L, void* base) {
   w.nlast = reinterpret_cast<uint32_t*>(b + L.off_nlast);
   w.tpre = reinterpret_cast<float*>(b + L.off_tpre);
   w.dcol = reinterpret_cast<float*>(b + L.off_dcol);
+  w.dden = reinterpret_cast<float*>(b + L.off_dden);
   return w;
 }
 
