@@ -15,7 +15,7 @@ namespace lv {
 // ------------------------------------------------------------------ setup
 __global__ void k_setup(RasterArgs a) {
   const int t = threadIdx.x;
-  if (t < kCounterWords) a.ws.counters[t] = 0u;
+  for (int k = t; k < kCounterWords; k += blockDim.x) a.ws.counters[k] = 0u;
   if (t == 0) {
     uint32_t tb = 0;
     uint64_t pb = 0;

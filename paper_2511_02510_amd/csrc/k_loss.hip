@@ -7,21 +7,28 @@
 // Every kernel runs on a (blocks, views) grid; a block finds its view's pixel
 // offset from the device camera array, so no host tables are needed and the
 // calls can be captured in a graph.
+#include <algorithm>
+
 #include "lv_common.h"
 #include "lv_select.h"
 
 namespace lv {
 
+constexpr int kUnroll = 8;
+// per-view weight sums are spread over kSumSlots slots, one 128-byte line
+// each (device atomics on one address serialise)
+constexpr int kSumSlots = 32;
+constexpr int kSumStride = 16;   // doubles
+
 struct LossWS {
   uint32_t* hist;    // [V][256]
   SelState* st;      // [V]
-  double* sums;      // [V]
-  uint32_t* done;    // blocks finished in the current histogram pass
+  double* sums;      // [V][kSumSlots][kSumStride]
 };
 
 uint64_t loss_ws_bytes(int V) {
   return align256(size_t(V) * 256 * 4) + align256(size_t(V) * sizeof(SelState)) +
-         align256(size_t(V) * 8) + 256;
+         align256(size_t(V) * kSumSlots * kSumStride * 8);
 }
 
 static LossWS loss_bind(void* base, int V) {
@@ -32,8 +39,6 @@ static LossWS loss_bind(void* base, int V) {
   w.st = reinterpret_cast<SelState*>(b);
   b += align256(size_t(V) * sizeof(SelState));
   w.sums = reinterpret_cast<double*>(b);
-  b += align256(size_t(V) * 8);
-  w.done = reinterpret_cast<uint32_t*>(b);
   return w;
 }
 
@@ -47,6 +52,7 @@ __global__ void k_loss_setup(const lv_camera* cams, int V, LossWS w, double q) {
   const int v = blockIdx.x;
   const uint64_t P = uint64_t(cams[v].width) * uint64_t(cams[v].height);
   w.hist[size_t(v) * 256 + threadIdx.x] = 0u;
+  if (threadIdx.x < kSumSlots) w.sums[(size_t(v) * kSumSlots + threadIdx.x) * kSumStride] = 0.0;
   if (threadIdx.x == 0) {
     double r = ceil(q * double(P));
     if (r < 1.0) r = 1.0;
@@ -55,8 +61,7 @@ __global__ void k_loss_setup(const lv_camera* cams, int V, LossWS w, double q) {
     w.st[v].k = P > 0 ? uint32_t(r) - 1u : 0u;
     w.st[v].n = uint32_t(P);
     w.st[v].valid = P > 0 ? 1u : 0u;
-    w.sums[v] = 0.0;
-    if (v == 0) *w.done = 0u;
+
   }
 }
 
@@ -67,72 +72,159 @@ __device__ __forceinline__ float grey_at(const float* img, uint64_t npv, int W, 
   return (img[p] + img[npv + p] + img[2 * npv + p]) * (1.0f / 3.0f);
 }
 
+// Each thread computes a column of kSobelRows pixels: it loads the grey
+// values of the 3 columns around its pixel over kSobelRows + 2 rows (borders
+// replicated) at once and slides the 3 x 3 window down; a block covers 256
+// consecutive columns of one row band.
+constexpr int kSobelRows = 8;
+
 __global__ __launch_bounds__(256) void k_sobel(const lv_camera* cams, const float* target, float* out) {
   const int v = blockIdx.y;
   const int W = cams[v].width, H = cams[v].height;
+  const uint32_t nxb = uint32_t(W + 255) / 256u;
+  if (blockIdx.x >= nxb * uint32_t((H + kSobelRows - 1) / kSobelRows)) return;
+  const int x = int(blockIdx.x % nxb) * 256 + int(threadIdx.x);
+  const int y0 = int(blockIdx.x / nxb) * kSobelRows;
+  if (x >= W) return;
   const uint64_t npv = uint64_t(W) * uint64_t(H);
   const uint64_t off = view_offset(cams, v);
   const float* img = target + 3 * off;
-  for (uint64_t p = uint64_t(blockIdx.x) * 256 + threadIdx.x; p < npv; p += uint64_t(gridDim.x) * 256) {
-    const int x = int(p % uint64_t(W)), y = int(p / uint64_t(W));
-    const float a00 = grey_at(img, npv, W, H, x - 1, y - 1), a10 = grey_at(img, npv, W, H, x, y - 1),
-                a20 = grey_at(img, npv, W, H, x + 1, y - 1);
-    const float a01 = grey_at(img, npv, W, H, x - 1, y), a21 = grey_at(img, npv, W, H, x + 1, y);
-    const float a02 = grey_at(img, npv, W, H, x - 1, y + 1), a12 = grey_at(img, npv, W, H, x, y + 1),
-                a22 = grey_at(img, npv, W, H, x + 1, y + 1);
+  float g[kSobelRows + 2][3];
+#pragma unroll
+  for (int r = 0; r < kSobelRows + 2; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) g[r][c] = grey_at(img, npv, W, H, x + c - 1, y0 + r - 1);
+#pragma unroll
+  for (int k = 0; k < kSobelRows; ++k) {
+    const int y = y0 + k;
+    if (y >= H) break;
+    const float a00 = g[k][0], a10 = g[k][1], a20 = g[k][2];
+    const float a01 = g[k + 1][0], a21 = g[k + 1][2];
+    const float a02 = g[k + 2][0], a12 = g[k + 2][1], a22 = g[k + 2][2];
     const float gx = (a20 + 2.0f * a21 + a22) - (a00 + 2.0f * a01 + a02);
     const float gy = (a02 + 2.0f * a12 + a22) - (a00 + 2.0f * a10 + a20);
-    out[off + p] = sqrtf(gx * gx + gy * gy);
+    out[off + uint64_t(y) * uint64_t(W) + uint64_t(x)] = sqrtf(gx * gx + gy * gy);
   }
 }
 
-// per-view histogram of the current digit of keys matching the prefix
+// per-view histogram of the current digit of keys matching the prefix; the
+// block counts into kHistCopies padded copies chosen by lane (most keys of a
+// view share the leading digits, and LDS atomics on one address run lane by
+// lane)
 __global__ __launch_bounds__(256) void k_hist_views(const lv_camera* cams, const float* vals,
                                                     LossWS w, int pass) {
-  __shared__ uint32_t lh[256];
+  __shared__ uint32_t lh[kHistCopies * kHistStride];
   const int v = blockIdx.y;
-  lh[threadIdx.x] = 0u;
+  for (int k = threadIdx.x; k < kHistCopies * kHistStride; k += 256) lh[k] = 0u;
   __syncthreads();
+  uint32_t* mine = lh + (threadIdx.x & (kHistCopies - 1)) * kHistStride;
   const SelState st = w.st[v];
   const uint64_t npv = uint64_t(cams[v].width) * uint64_t(cams[v].height);
   const uint64_t off = view_offset(cams, v);
   const int sh = sel_shift(pass);
   const uint32_t hm = sel_himask(pass);
-  for (uint64_t p = uint64_t(blockIdx.x) * 256 + threadIdx.x; p < npv; p += uint64_t(gridDim.x) * 256) {
-    const uint32_t key = f2key(vals[off + p]);
-    if ((key & hm) == st.prefix) atomicAdd(&lh[(key >> sh) & 255u], 1u);
+  // kUnroll independent coalesced loads per thread and step keep enough
+  // requests in flight with few blocks (a view has fewer than 2^32 pixels)
+  const float* src = vals + off;
+  const uint32_t np32 = uint32_t(npv), step = gridDim.x * (256u * kUnroll);
+  for (uint32_t base = blockIdx.x * (256u * kUnroll) + threadIdx.x; base < np32; base += step) {
+    float vv[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const uint32_t i = base + uint32_t(u) * 256u;
+      vv[u] = i < np32 ? src[i] : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      if (base + uint32_t(u) * 256u >= np32) break;
+      const uint32_t key = f2key(vv[u]);
+      if ((key & hm) == st.prefix) atomicAdd(&mine[(key >> sh) & 255u], 1u);
+    }
   }
   __syncthreads();
-  const uint32_t c = lh[threadIdx.x];
+  uint32_t c = 0;
+#pragma unroll
+  for (int i = 0; i < kHistCopies; ++i) c += lh[i * kHistStride + threadIdx.x];
   if (c) atomicAdd(&w.hist[size_t(v) * 256 + threadIdx.x], c);
-  sel_finish_pass(w.st, w.hist, gridDim.y, pass, w.done);
+}
+
+__global__ __launch_bounds__(256) void k_sel_step(SelState* st, uint32_t* hist, int nseg, int pass) {
+  const int sg = int(blockIdx.x) * 4 + int(threadIdx.x >> 6);
+  if (sg >= nseg) return;
+  const int lane = threadIdx.x & 63;
+  SelState* S = st + sg;
+  uint32_t* h = hist + size_t(sg) * 256 + 4 * lane;
+  const uint4 c4 = *reinterpret_cast<const uint4*>(h);
+  const uint32_t c[4] = {c4.x, c4.y, c4.z, c4.w};
+  const uint32_t tot = (c[0] + c[1]) + (c[2] + c[3]);
+  uint32_t incl = tot;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  const uint32_t excl = incl - tot;
+  const uint32_t k = S->k;
+  if (S->valid != 0 && excl <= k && k < incl) {   // the one lane whose bins hold rank k
+    uint32_t e = excl, d = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < 3; ++j) {
+      if (d == j && k >= e + c[j]) { e += c[j]; d = j + 1; }
+    }
+    S->prefix = S->prefix | ((4u * uint32_t(lane) + d) << sel_shift(pass));
+    S->k = k - e;
+  }
+  *reinterpret_cast<uint4*>(h) = make_uint4(0u, 0u, 0u, 0u);
+}
+
+hipError_t launch_sel_step(SelState* st, uint32_t* hist, int nseg, int pass, hipStream_t s) {
+  if (nseg <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sel_step, dim3((nseg + 3) / 4), dim3(256), 0, s, st, hist, nseg, pass);
+  return hipGetLastError();
+}
+
+// b^gamma for b > 0 through the hardware log2 / exp2 (relative error a few
+// 1e-7 for the bases and exponents used here)
+__device__ __forceinline__ float pow_pos(float b, float gamma) {
+  return __builtin_amdgcn_exp2f(gamma * __builtin_amdgcn_logf(b));
 }
 
 __global__ __launch_bounds__(256) void k_lf_weight(const lv_camera* cams, float* wbuf, LossWS w,
                                                    float gamma, int form, float eps) {
   __shared__ double s_part[4];
   const int v = blockIdx.y;
-  const uint64_t npv = uint64_t(cams[v].width) * uint64_t(cams[v].height);
-  const uint64_t off = view_offset(cams, v);
+  const uint32_t np32 = uint32_t(cams[v].width) * uint32_t(cams[v].height);
+  float* wv = wbuf + view_offset(cams, v);
   const float g99 = key2f(w.st[v].prefix);
   double part = 0.0;
-  for (uint64_t p = uint64_t(blockIdx.x) * 256 + threadIdx.x; p < npv; p += uint64_t(gridDim.x) * 256) {
-    const float g = wbuf[off + p];
-    const float ratio = g99 > 0.0f ? g / g99 : 0.0f;
-    float wt;
-    if (form == 0) wt = powf(eps + 1.0f - fminf(1.0f, ratio), gamma);
-    else wt = powf(1.0f + ratio, -gamma);
-    wbuf[off + p] = wt;
-    part += double(wt);
+  constexpr int U = 4;
+  const uint32_t step = gridDim.x * (256u * U);
+  for (uint32_t base = blockIdx.x * (256u * U) + threadIdx.x; base < np32; base += step) {
+    float g[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t i = base + uint32_t(u) * 256u;
+      g[u] = i < np32 ? wv[i] : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t i = base + uint32_t(u) * 256u;
+      if (i >= np32) break;
+      const float ratio = g99 > 0.0f ? g[u] / g99 : 0.0f;
+      const float wt = form == 0 ? pow_pos(eps + 1.0f - fminf(1.0f, ratio), gamma)
+                                 : pow_pos(1.0f + ratio, -gamma);
+      wv[i] = wt;
+      part += double(wt);
+    }
   }
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wvi = threadIdx.x >> 6;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
-  if (lane == 0) s_part[wv] = part;
+  if (lane == 0) s_part[wvi] = part;
   __syncthreads();
   if (threadIdx.x == 0) {
-    const double s = s_part[0] + s_part[1] + s_part[2] + s_part[3];
-    unsafeAtomicAdd(&w.sums[v], s);
+    const double sum = s_part[0] + s_part[1] + s_part[2] + s_part[3];
+    unsafeAtomicAdd(&w.sums[(size_t(v) * kSumSlots + blockIdx.x % kSumSlots) * kSumStride], sum);
   }
 }
 
@@ -140,26 +232,51 @@ __global__ __launch_bounds__(256) void k_lf_norm(const lv_camera* cams, float* w
   const int v = blockIdx.y;
   const uint64_t npv = uint64_t(cams[v].width) * uint64_t(cams[v].height);
   const uint64_t off = view_offset(cams, v);
-  const float scale = float(double(npv) / w.sums[v]);
+  double sum = 0.0;
+  for (int i = 0; i < kSumSlots; ++i) sum += w.sums[(size_t(v) * kSumSlots + i) * kSumStride];
+  const float scale = float(double(npv) / sum);
   for (uint64_t p = uint64_t(blockIdx.x) * 256 + threadIdx.x; p < npv; p += uint64_t(gridDim.x) * 256)
     wbuf[off + p] *= scale;
 }
 
+// blocks per view: enough waves in flight for the streaming kernels (each
+// block still loops over several pixels, so per-block partial sums and
+// histograms meet in few global atomics)
 static uint32_t blocks_for(uint64_t max_pix) {
-  uint64_t b = (max_pix + 1023) / 1024;
+  uint64_t b = (max_pix + 2047) / 2048;
   if (b < 1) b = 1;
-  if (b > 96) b = 96;   // few long-running blocks: per-block partial sums meet in few atomics
+  if (b > 512) b = 512;
   return uint32_t(b);
 }
 
-hipError_t run_lf_weight(const lv_camera* cams_dev, int V, uint64_t max_pix, const float* target,
-                         float gamma, int form, float eps, float* weight, void* ws, hipStream_t s) {
+// blocks per view of the histogram passes: every block adds its nonzero bins
+// to the view's global bins, so these passes use fewer, longer-running blocks
+constexpr uint32_t kHistBlocks = 128;
+static uint32_t hist_blocks_for(uint64_t max_pix) {
+  const uint32_t b = blocks_for(max_pix);
+  return b < kHistBlocks ? b : kHistBlocks;
+}
+
+hipError_t run_lf_weight(const lv_camera* cams_dev, const lv_camera* cams_host, int V,
+                         const float* target, float gamma, int form, float eps, float* weight,
+                         void* ws, hipStream_t s) {
+  uint64_t max_pix = 0, max_sobel_blocks = 0;
+  for (int v = 0; v < V; ++v) {
+    const uint64_t W = uint64_t(cams_host[v].width), H = uint64_t(cams_host[v].height);
+    max_pix = std::max(max_pix, W * H);
+    max_sobel_blocks = std::max(max_sobel_blocks, ((W + 255) / 256) * ((H + kSobelRows - 1) / kSobelRows));
+  }
   LossWS w = loss_bind(ws, V);
   const dim3 grid(blocks_for(max_pix), V);
   hipLaunchKernelGGL(k_loss_setup, dim3(V), dim3(256), 0, s, cams_dev, V, w, 0.99);
-  hipLaunchKernelGGL(k_sobel, grid, dim3(256), 0, s, cams_dev, target, weight);
-  for (int pass = 0; pass < 4; ++pass)
-    hipLaunchKernelGGL(k_hist_views, grid, dim3(256), 0, s, cams_dev, (const float*)weight, w, pass);
+  hipLaunchKernelGGL(k_sobel, dim3(uint32_t(max_sobel_blocks), V), dim3(256), 0, s, cams_dev, target,
+                     weight);
+  const dim3 hgrid(hist_blocks_for(max_pix), V);
+  for (int pass = 0; pass < 4; ++pass) {
+    hipLaunchKernelGGL(k_hist_views, hgrid, dim3(256), 0, s, cams_dev, (const float*)weight, w, pass);
+    const hipError_t e = launch_sel_step(w.st, w.hist, V, pass, s);
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(k_lf_weight, grid, dim3(256), 0, s, cams_dev, weight, w, gamma, form, eps);
   hipLaunchKernelGGL(k_lf_norm, grid, dim3(256), 0, s, cams_dev, weight, w);
   return hipGetLastError();
@@ -176,24 +293,43 @@ __global__ __launch_bounds__(256) void k_l1_grad(const lv_camera* cams, const fl
                                                  float* loss, float* d_rgb) {
   __shared__ float s_part[4];
   const int v = blockIdx.y;
-  const uint64_t npv = uint64_t(cams[v].width) * uint64_t(cams[v].height);
+  const uint32_t npv = uint32_t(cams[v].width) * uint32_t(cams[v].height);
   const uint64_t off = view_offset(cams, v);
   const float inv3p = float(1.0 / (3.0 * double(npv)));
   const float* C = rgb + 3 * off;
   const float* I = target + 3 * off;
+  const float* Wt = weight + off;
   float* G = d_rgb + 3 * off;
   float part = 0.0f;
-  for (uint64_t p = uint64_t(blockIdx.x) * 256 + threadIdx.x; p < npv; p += uint64_t(gridDim.x) * 256) {
-    const float wt = weight[off + p];
-    float s = 0.0f;
+  constexpr int U = 2;
+  const uint32_t step = gridDim.x * (256u * U);
+  for (uint32_t base = blockIdx.x * (256u * U) + threadIdx.x; base < npv; base += step) {
+    float c[U][3], t[U][3], wt[U];
 #pragma unroll
-    for (int ch = 0; ch < 3; ++ch) {
-      const float r = C[ch * npv + p] - I[ch * npv + p];
-      s += fabsf(r);
-      const float sg = r > 0.0f ? 1.0f : (r < 0.0f ? -1.0f : 0.0f);
-      G[ch * npv + p] = wt * sg * inv3p;
+    for (int u = 0; u < U; ++u) {
+      const uint32_t p = base + uint32_t(u) * 256u;
+      const bool in = p < npv;
+      wt[u] = in ? Wt[p] : 0.0f;
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        c[u][ch] = in ? C[size_t(ch) * npv + p] : 0.0f;
+        t[u][ch] = in ? I[size_t(ch) * npv + p] : 0.0f;
+      }
     }
-    part = fmaf(wt, s, part);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t p = base + uint32_t(u) * 256u;
+      if (p >= npv) break;
+      float sabs = 0.0f;
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        const float r = c[u][ch] - t[u][ch];
+        sabs += fabsf(r);
+        const float sg = r > 0.0f ? 1.0f : (r < 0.0f ? -1.0f : 0.0f);
+        G[size_t(ch) * npv + p] = wt[u] * sg * inv3p;
+      }
+      part = fmaf(wt[u], sabs, part);
+    }
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
@@ -204,11 +340,18 @@ __global__ __launch_bounds__(256) void k_l1_grad(const lv_camera* cams, const fl
     unsafeAtomicAdd(&loss[v], (s_part[0] + s_part[1] + s_part[2] + s_part[3]) * inv3p);
 }
 
+// blocks per view of the L1 pass: each block ends with one atomic add into
+// the view's loss (the views' losses share a cache line)
+static uint32_t l1_blocks_for(uint64_t max_pix) {
+  const uint32_t b = blocks_for(max_pix);
+  return b < 128u ? b : 128u;
+}
+
 hipError_t run_l1_grad(const lv_camera* cams_dev, int V, uint64_t max_pix, const float* rgb,
                        const float* target, const float* weight, float* loss, float* d_rgb,
                        hipStream_t s) {
   hipLaunchKernelGGL(k_zero_f32, dim3((V + 255) / 256), dim3(256), 0, s, loss, V);
-  hipLaunchKernelGGL(k_l1_grad, dim3(blocks_for(max_pix), V), dim3(256), 0, s, cams_dev, rgb,
+  hipLaunchKernelGGL(k_l1_grad, dim3(l1_blocks_for(max_pix), V), dim3(256), 0, s, cams_dev, rgb,
                      target, weight, loss, d_rgb);
   return hipGetLastError();
 }

@@ -21,12 +21,11 @@ struct QuantWS {
   uint32_t* hist;     // [2 + B][256]
   SelState* st;       // [2 + B]: p5, p95, bins
   uint32_t* cnt;      // [B]
-  uint32_t* done;     // blocks finished in the current pass
 };
 
 uint64_t quant_ws_bytes(int64_t n, int B) {
   return align256(4 * size_t(n)) * 2 + align256(size_t(n)) + align256(size_t(2 + B) * 1024) +
-         align256(size_t(2 + B) * sizeof(SelState)) + align256(4 * size_t(B)) + 256;
+         align256(size_t(2 + B) * sizeof(SelState)) + align256(4 * size_t(B));
 }
 
 static QuantWS quant_bind(void* base, int64_t n, int B) {
@@ -37,10 +36,12 @@ static QuantWS quant_bind(void* base, int64_t n, int B) {
   w.bins = reinterpret_cast<uint8_t*>(b); b += align256(size_t(n));
   w.hist = reinterpret_cast<uint32_t*>(b); b += align256(size_t(2 + B) * 1024);
   w.st = reinterpret_cast<SelState*>(b); b += align256(size_t(2 + B) * sizeof(SelState));
-  w.cnt = reinterpret_cast<uint32_t*>(b); b += align256(4 * size_t(B));
-  w.done = reinterpret_cast<uint32_t*>(b);
+  w.cnt = reinterpret_cast<uint32_t*>(b);
   return w;
 }
+
+constexpr int kMaxBins = 64;   // n_bins accepted by the entry point
+constexpr int kUnroll = 8;
 
 __device__ __forceinline__ uint32_t rank_of(double q, uint32_t n) {
   double r = ceil(q * double(n));
@@ -58,7 +59,6 @@ __global__ void k_q_setup(QuantWS w, int B, uint32_t n) {
     w.st[s].valid = (s < 2 && n > 0) ? 1u : 0u;
     w.st[s].k = s == 0 ? rank_of(0.05, n) : (s == 1 ? rank_of(0.95, n) : 0u);
     if (s >= 2) w.cnt[s - 2] = 0u;
-    if (s == 0) *w.done = 0u;
   }
 }
 
@@ -86,39 +86,62 @@ __global__ __launch_bounds__(256) void k_q_delta(RasterArgs a, QuantWS w) {
 
 // Histogram of the current digit.  dual: every element counts towards
 // segments seg0 and seg0 + 1 (p5 and p95 of the same keys); otherwise the
-// element's segment is seg0 + label (label 0 when labels is null).
+// element's segment is seg0 + label (label 0 when labels is null).  The
+// block counts into ncopy padded lane-indexed copies of its nseg x 256 bins.
 __global__ __launch_bounds__(256) void k_q_hist(const uint32_t* keys, const uint8_t* labels, int64_t n,
-                                                QuantWS w, int seg0, int nseg, int pass, int dual) {
+                                                QuantWS w, int seg0, int nseg, int pass, int dual,
+                                                int ncopy) {
   extern __shared__ uint32_t lh[];
-  for (int k = threadIdx.x; k < nseg * 256; k += 256) lh[k] = 0u;
+  const int stride = nseg * 256 + (ncopy > 1 ? 1 : 0);
+  for (int k = threadIdx.x; k < ncopy * stride; k += 256) lh[k] = 0u;
+  __syncthreads();
+  uint32_t* mine = lh + (threadIdx.x & (ncopy - 1)) * stride;
+  // segment states in LDS (a binned element looks its segment up by label)
+  __shared__ uint32_t s_pre[2 + kMaxBins], s_ok[2 + kMaxBins];
+  for (int k = threadIdx.x; k < nseg; k += 256) {
+    s_pre[k] = w.st[seg0 + k].prefix;
+    s_ok[k] = w.st[seg0 + k].valid;
+  }
   __syncthreads();
   const int sh = sel_shift(pass);
   const uint32_t hm = sel_himask(pass);
-  const SelState* st = w.st + seg0;
-  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
-    const uint32_t key = keys[i];
-    const uint32_t d = (key >> sh) & 255u;
-    if (dual) {
-      if (st[0].valid && (key & hm) == st[0].prefix) atomicAdd(&lh[d], 1u);
-      if (st[1].valid && (key & hm) == st[1].prefix) atomicAdd(&lh[256 + d], 1u);
-    } else {
-      const int s = labels ? int(labels[i]) : 0;
-      if (st[s].valid && (key & hm) == st[s].prefix) atomicAdd(&lh[s * 256 + d], 1u);
+  // kUnroll independent coalesced loads per thread and step keep enough
+  // requests in flight with one or two blocks per CU
+  const int64_t step = int64_t(gridDim.x) * (256 * kUnroll);
+  for (int64_t base = int64_t(blockIdx.x) * (256 * kUnroll) + threadIdx.x; base < n; base += step) {
+    uint32_t kk[kUnroll];
+    int ss[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int64_t i = base + int64_t(u) * 256;
+      kk[u] = i < n ? keys[i] : 0u;
+      ss[u] = (i < n && !dual && labels) ? int(labels[i]) : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      if (base + int64_t(u) * 256 >= n) break;
+      const uint32_t key = kk[u];
+      const uint32_t d = (key >> sh) & 255u;
+      if (dual) {
+        if (s_ok[0] && (key & hm) == s_pre[0]) atomicAdd(&mine[d], 1u);
+        if (s_ok[1] && (key & hm) == s_pre[1]) atomicAdd(&mine[256 + d], 1u);
+      } else {
+        const int sg = ss[u];
+        if (s_ok[sg] && (key & hm) == s_pre[sg]) atomicAdd(&mine[sg * 256 + d], 1u);
+      }
     }
   }
   __syncthreads();
   for (int k = threadIdx.x; k < nseg * 256; k += 256) {
-    const uint32_t c = lh[k];
+    uint32_t c = 0;
+    for (int i = 0; i < ncopy; ++i) c += lh[i * stride + k];
     if (c) atomicAdd(&w.hist[size_t(seg0) * 256 + k], c);
   }
-  sel_finish_pass(w.st + seg0, w.hist + size_t(seg0) * 256, nseg, pass, w.done);
 }
 
-// bins from delta and (p5, p95); the last block turns the bin counts into the
-// per-bin selection ranks
-__global__ __launch_bounds__(256) void k_q_bins(int64_t n, int B, double q, QuantWS w, uint8_t* out_bins) {
+// bins from delta and (p5, p95), with the per-bin counts
+__global__ __launch_bounds__(256) void k_q_bins(int64_t n, int B, QuantWS w, uint8_t* out_bins) {
   extern __shared__ uint32_t lc[];
-  __shared__ uint32_t s_last;
   for (int k = threadIdx.x; k < B; k += 256) lc[k] = 0u;
   __syncthreads();
   const float p5 = key2f(w.st[0].prefix), p95 = key2f(w.st[1].prefix);
@@ -144,22 +167,18 @@ __global__ __launch_bounds__(256) void k_q_bins(int64_t n, int B, double q, Quan
   __syncthreads();
   for (int k = threadIdx.x; k < B; k += 256)
     if (lc[k]) atomicAdd(&w.cnt[k], lc[k]);
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) s_last = (atomicAdd(w.done, 1u) == gridDim.x - 1u) ? 1u : 0u;
-  __syncthreads();
-  if (s_last) {
-    __threadfence();
-    for (int b = threadIdx.x; b < B; b += 256) {
-      const uint32_t c = __hip_atomic_load(&w.cnt[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      SelState& st = w.st[2 + b];
-      st.prefix = 0u;
-      st.n = c;
-      st.valid = c > 0 ? 1u : 0u;
-      st.k = c > 0 ? rank_of(q, c) : 0u;
-    }
-    if (threadIdx.x == 0) *w.done = 0u;
-  }
+}
+
+// per-bin selection state from the bin counts
+__global__ void k_q_ranks(int B, double q, QuantWS w) {
+  const int b = threadIdx.x;
+  if (b >= B) return;
+  const uint32_t c = w.cnt[b];
+  SelState& st = w.st[2 + b];
+  st.prefix = 0u;
+  st.n = c;
+  st.valid = c > 0 ? 1u : 0u;
+  st.k = c > 0 ? rank_of(q, c) : 0u;
 }
 
 __global__ __launch_bounds__(256) void k_q_prune(int64_t n, int B, QuantWS w, const float* wmax,
@@ -173,6 +192,17 @@ __global__ __launch_bounds__(256) void k_q_prune(int64_t n, int B, QuantWS w, co
   const SelState st = w.st[2 + w.bins[i]];
   const float t = st.valid ? key2f(st.prefix) : -INFINITY;
   prune[i] = wmax[i] <= t ? 1u : 0u;
+}
+
+// histogram copies: as many as fit in 64 KB of LDS, at most 16
+constexpr int kCopiesDual = 16;
+static size_t hist_lds(int nseg, int ncopy) {
+  return size_t(ncopy) * (size_t(nseg) * 256 + (ncopy > 1 ? 1 : 0)) * 4;
+}
+static int binned_copies(int B) {
+  int c = 16;
+  while (c > 1 && hist_lds(B, c) > 65536) c >>= 1;
+  return c;
 }
 
 static uint32_t grid_for(int64_t n) {
@@ -191,13 +221,22 @@ hipError_t run_depth_quantile(const RasterArgs& a, int B, double q, void* ws, fl
     hipLaunchKernelGGL(k_q_delta, dim3(uint32_t((a.n + 255) / 256)), dim3(256), 0, s, a, w);
     const uint32_t g = grid_for(a.n);
     // p5 and p95 of delta: segments 0 and 1 over every voxel, in the same passes
-    for (int pass = 0; pass < 4; ++pass)
-      hipLaunchKernelGGL(k_q_hist, dim3(g), dim3(256), 2 * 256 * 4, s, (const uint32_t*)w.dkey,
-                         (const uint8_t*)nullptr, a.n, w, 0, 2, pass, 1);
-    hipLaunchKernelGGL(k_q_bins, dim3(g), dim3(256), B * 4, s, a.n, B, q, w, out_bins);
-    for (int pass = 0; pass < 4; ++pass)
-      hipLaunchKernelGGL(k_q_hist, dim3(g), dim3(256), size_t(B) * 256 * 4, s,
-                         (const uint32_t*)w.wkey, (const uint8_t*)w.bins, a.n, w, 2, B, pass, 0);
+    for (int pass = 0; pass < 4; ++pass) {
+      hipLaunchKernelGGL(k_q_hist, dim3(g), dim3(256), hist_lds(2, kCopiesDual), s,
+                         (const uint32_t*)w.dkey, (const uint8_t*)nullptr, a.n, w, 0, 2, pass, 1,
+                         kCopiesDual);
+      const hipError_t e = launch_sel_step(w.st, w.hist, 2, pass, s);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_q_bins, dim3(g), dim3(256), B * 4, s, a.n, B, w, out_bins);
+    hipLaunchKernelGGL(k_q_ranks, dim3(1), dim3(64), 0, s, B, q, w);
+    const int cb = binned_copies(B);
+    for (int pass = 0; pass < 4; ++pass) {
+      hipLaunchKernelGGL(k_q_hist, dim3(g), dim3(256), hist_lds(B, cb), s, (const uint32_t*)w.wkey,
+                         (const uint8_t*)w.bins, a.n, w, 2, B, pass, 0, cb);
+      const hipError_t e = launch_sel_step(w.st + 2, w.hist + 2 * 256, B, pass, s);
+      if (e != hipSuccess) return e;
+    }
   }
   hipLaunchKernelGGL(k_q_prune, dim3(uint32_t((a.n + 255) / 256) > 0 ? uint32_t((a.n + 255) / 256) : 1u),
                      dim3(256), 0, s, a.n, B, w, a.wmax, tau, prune);

@@ -253,6 +253,31 @@ __device__ __forceinline__ bool seg_reduce_rows(float* v, int jj, bool pend) {
   return last;
 }
 
+// ------------------------------------------------------------ tile queues
+// The longest-first tile order is dealt round-robin to nq = min(kQueues,
+// blocks) queues; block b pops queue b mod nq, whose j-th entry is order
+// position q + j nq.  Every queue has at least one block (the grid has at
+// least nq blocks), so every tile is taken exactly once.  pop() returns an
+// order position, or T once the block's queue is exhausted.
+struct TileQueue {
+  uint32_t* head;
+  uint32_t q, nq, len, T;
+  __device__ uint32_t pop() const {
+    const uint32_t j = atomicAdd(head, 1u);
+    return j < len ? q + j * nq : T;
+  }
+};
+
+__device__ __forceinline__ TileQueue tile_queue(uint32_t T, uint32_t* heads) {
+  TileQueue tq;
+  tq.nq = gridDim.x < uint32_t(kQueues) ? gridDim.x : uint32_t(kQueues);
+  tq.q = blockIdx.x % tq.nq;
+  tq.len = T > tq.q ? (T - tq.q + tq.nq - 1) / tq.nq : 0u;
+  tq.head = heads + tq.q * kQueueStride;
+  tq.T = T;
+  return tq;
+}
+
 // ======================================================================
 // forward
 struct FwdState {
@@ -296,13 +321,14 @@ __global__ __launch_bounds__(TS* TS) void k_composite_fwd(RasterArgs a) {
   const int wbx = (wave % BPR) * 8, wby = (wave / BPR) * 8;
 
   // the next queue slot is taken while the current tile is processed; a
-  // block stops at the first slot past the end (every later one is too)
+  // block stops at the first slot past the end of its queue
+  const TileQueue tq = tile_queue(a.T, a.ws.counters + C_QFWD);
   uint32_t next = 0;
-  if (threadIdx.x == 0) next = atomicAdd(&a.ws.counters[C_QFWD], 1u);
+  if (threadIdx.x == 0) next = tq.pop();
   for (;;) {
     if (threadIdx.x == 0) {
       s_tile = next;
-      next = atomicAdd(&a.ws.counters[C_QFWD], 1u);
+      next = tq.pop();
     }
     __syncthreads();
     const uint32_t qi = s_tile;
@@ -457,12 +483,13 @@ __global__ __launch_bounds__(TS* TS) void k_composite_bwd(RasterArgs a) {
   const int wbx = (wave % BPR) * 8, wby = (wave / BPR) * 8;
   const float bg[3] = {a.bg[0], a.bg[1], a.bg[2]};
 
+  const TileQueue tq = tile_queue(a.T, a.ws.counters + C_QBWD);
   uint32_t next = 0;
-  if (threadIdx.x == 0) next = atomicAdd(&a.ws.counters[C_QBWD], 1u);
+  if (threadIdx.x == 0) next = tq.pop();
   for (;;) {
     if (threadIdx.x == 0) {
       s_tile = next;
-      next = atomicAdd(&a.ws.counters[C_QBWD], 1u);
+      next = tq.pop();
       s_maxn = 0u;
     }
     __syncthreads();

@@ -13,7 +13,7 @@ hipError_t launch_bwd_setup(const RasterArgs& a, hipStream_t s) {
   if (e != hipSuccess) return e;
   e = launch_fill_u32(reinterpret_cast<uint32_t*>(a.ws.dcol), 3ull * uint64_t(a.n) * uint64_t(a.V), 0u, s);
   if (e != hipSuccess) return e;
-  return launch_fill_u32(a.ws.counters + C_QBWD, 1, 0u, s);
+  return launch_fill_u32(a.ws.counters + C_QBWD, uint64_t(kQueues) * kQueueStride, 0u, s);
 }
 
 template <int DEG>

@@ -14,8 +14,9 @@
 namespace lv {
 uint64_t loss_ws_bytes(int V);
 uint64_t quant_ws_bytes(int64_t n, int B);
-hipError_t run_lf_weight(const lv_camera* cams_dev, int V, uint64_t max_pix, const float* target,
-                         float gamma, int form, float eps, float* weight, void* ws, hipStream_t s);
+hipError_t run_lf_weight(const lv_camera* cams_dev, const lv_camera* cams_host, int V,
+                         const float* target, float gamma, int form, float eps, float* weight,
+                         void* ws, hipStream_t s);
 hipError_t run_l1_grad(const lv_camera* cams_dev, int V, uint64_t max_pix, const float* rgb,
                        const float* target, const float* weight, float* loss, float* d_rgb,
                        hipStream_t s);
@@ -406,8 +407,8 @@ lv_status lv_lf_weight(lv_context* ctx, const lv_frame* frame, const float* targ
   if (form != 0 && form != 1) return fail(ctx, LV_ERR_ARG, "form must be 0 or 1");
   if (!std::isfinite(gamma) || !std::isfinite(eps) || eps < 0.0f)
     return fail(ctx, LV_ERR_ARG, "gamma must be finite and eps >= 0");
-  LV_TRY(lv::run_lf_weight(frame->cams_dev, frame->n_views, max_view_pixels(frame), target, gamma,
-                           form, eps, weight, workspace, stream), "lf_weight");
+  LV_TRY(lv::run_lf_weight(frame->cams_dev, frame->cams_host, frame->n_views, target, gamma, form,
+                           eps, weight, workspace, stream), "lf_weight");
   return LV_OK;
 }
 

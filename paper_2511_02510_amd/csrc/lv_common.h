@@ -14,7 +14,12 @@ constexpr int kIdBits = 28;           // voxel id bits in a sort key
 constexpr uint32_t kIdMask = (1u << kIdBits) - 1u;
 constexpr int kSortCap = 2048;        // longest tile list sorted in one LDS pass
 constexpr float kZNear = 1e-4f;       // binning near plane (camera-space z)
-constexpr int kCounterWords = 128;
+// Tile queues of the composite passes: kQueues interleaved queues, each head
+// in its own 128-byte line (same-address device atomics serialise at about
+// 12 ns each, and one head popped once per tile would throttle the pass).
+constexpr int kQueues = 16;
+constexpr int kQueueStride = 32;   // words
+constexpr int kCounterWords = 128 + 2 * kQueues * kQueueStride;
 // Each tile has kSpread pair counters (chosen by voxel id & (kSpread - 1)),
 // stored sub-counter-major so that the atomics on one tile's counters fall on
 // different cache lines; the scan visits them tile-major, so every tile's
@@ -55,11 +60,11 @@ struct Rec {
 enum Counter : int {
   C_PAIRS = 0,       // number of (tile, voxel) pairs (saturating below 2^32)
   C_OVERFLOW = 1,    // 1 if pairs > capacity
-  C_QFWD = 2,        // forward tile queue head
-  C_QBWD = 3,        // backward tile queue head
   C_BUCKET = 8,      // [32] tile counts per length bucket
   C_BSTART = 40,     // [33] bucket starts
   C_BFILL = 80,      // [32] bucket cursors
+  C_QFWD = 128,      // [kQueues] forward tile queue heads, kQueueStride apart
+  C_QBWD = 128 + kQueues * kQueueStride,   // [kQueues] backward queue heads
 };
 
 // Workspace layout, computed identically on the host for sizing and launch.
