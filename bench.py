@@ -43,6 +43,116 @@ def composite_bytes(Q, P, which):
     return 72 * Q + 44 * Q + 20 * P
 
 
+PROFILE_MD = os.path.join(ROOT, "profiles", "composite_hbm_counters_ring1m.md")
+
+
+def composite_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("paper_2511_02510_amd/csrc/k_raster.hip", "paper_2511_02510_amd/csrc/lv_common.h"):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(kernel, tile, chunk):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE/WRITE_SIZE
+    summary, or None when it was taken on other kernel sources or settings."""
+    try:
+        with open(PROFILE_MD) as fh:
+            text = fh.read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        f = line.split()
+        if len(f) >= 2 and f[0] in ("traffic_bytes_per_launch", "composite_source_sha256_16", "settings"):
+            vals[(f[0], f[1] if f[0] == "traffic_bytes_per_launch" else "")] = f[1:]
+    if vals.get(("composite_source_sha256_16", ""), [None])[0] != composite_source_hash():
+        return None
+    if vals.get(("settings", ""), []) != [f"tile={tile}", f"chunk={chunk}"]:
+        return None
+    t = vals.get(("traffic_bytes_per_launch", "k_" + kernel))
+    return int(float(t[1])) if t else None
+
+
+# SURVEY-style algorithmic bytes of the whole forward and backward (all
+# phases): N voxels, M visible (view, voxel) records, Q pairs, P pixels,
+# K SH floats per voxel
+def step_bytes(N, M, Q, P, K):
+    b_fwd = N * (7 + 32 + 4 * K) + 4 * N + 20 * M + 91 * Q + 28 * P
+    b_bwd = 107 * Q + 28 * P + 24 * M + (7 + 32 + 4 * K) * N
+    return b_fwd, b_bwd
+
+
+def measure_workload(lv, ctx, name, tile, chunk, reps, warmup, quantile, form, gamma):
+    """Forward and whole-step MP/s of another named workload (graph replay)."""
+    import torch
+    import synth
+    t0 = time.time()
+    scene, cams, targets = synth.make_config(name)
+    gen_s = time.time() - t0
+    dev = torch.device("cuda", 0)
+    vox = lv.Voxels.from_scene(scene, dev)
+    frame = lv.Frame(cams, dev)
+    P = frame.P
+    target = torch.from_numpy(np.concatenate([t.ravel() for t in targets]).astype(np.float32)).to(dev)
+    r = lv.Renderer(ctx, vox, frame, lv.settings(tile=tile, chunk=chunk))
+    rgb, depth, alpha = r.new_outputs()
+    wmax = torch.zeros(vox.n, device=dev)
+    weight = torch.empty(P, device=dev)
+    lw_ws = torch.empty(lv.lf_weight_workspace_size(frame.n_views), dtype=torch.uint8, device=dev)
+    loss = torch.empty(frame.n_views, device=dev)
+    d_rgb = torch.empty(3 * P, device=dev)
+    dd, dsh = torch.empty_like(vox.density), torch.empty_like(vox.sh)
+    nb = 16
+    q_ws = torch.empty(lv.quantile_workspace_size(vox.n, nb), dtype=torch.uint8, device=dev)
+    tau = torch.empty(nb, device=dev)
+    prune = torch.empty(vox.n, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.Stream()
+
+    def fwd(verify=False):
+        r.forward(rgb, depth, alpha, wmax, stream=stream, verify=verify)
+
+    def step(verify=False):
+        fwd(verify)
+        lv.lf_weight(ctx, frame, target, gamma, form, 1e-3, weight, lw_ws, stream=stream)
+        lv.l1_grad(ctx, frame, rgb, target, weight, loss, d_rgb, stream=stream)
+        r.backward(d_rgb, None, None, dd, dsh, stream=stream)
+        if quantile:
+            lv.depth_quantile(ctx, vox, frame, wmax, nb, 0.1, q_ws, tau, prune, stream=stream)
+
+    def timed(fn):
+        with torch.cuda.stream(stream):
+            fn(verify=True)
+        torch.cuda.synchronize()
+        lv.graph_begin(ctx, stream)
+        fn()
+        lv.graph_end(ctx, stream)
+        for _ in range(warmup):
+            lv.graph_launch(ctx, stream)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            lv.graph_launch(ctx, stream)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t) / reps
+        lv.graph_reset(ctx)
+        return ms
+
+    fwd_ms = timed(fwd)
+    out = {"voxels": scene.n, "views": len(cams), "px": P, "fwd_ms": round(fwd_ms, 4),
+           "fwd_mp_s": round(P / fwd_ms / 1e3, 2)}
+    if name != "shell200k":          # that configuration is forward + w_max only
+        step_ms = timed(step)
+        out.update({"fwdbwd_ms": round(step_ms, 4), "fwdbwd_mp_s": round(P / step_ms / 1e3, 2),
+                    "step": "fwd + lf_weight + l1 + bwd" + (" + depth quantile" if quantile else "")})
+    log(f"[bench] {name}: {out} (scene generated in {gen_s:.1f} s)")
+    del r, vox, frame, target
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -55,6 +165,9 @@ def main():
     ap.add_argument("--cpu-sample-views", type=int, default=1)
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="if > 0: only run this many eager steps (for rocprofv3) and exit")
+    ap.add_argument("--other-workloads", default="grid4k,shell200k,shell200k_train,hemi4m",
+                    help="comma list of further workloads to report fwd and fwd+bwd MP/s for "
+                         "(empty: none)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="if > 0: only copy this many MiB device-to-device 3 times (a kernel of "
                          "known traffic that calibrates the HBM byte counters) and exit")
@@ -215,8 +328,27 @@ def main():
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
             "alg_bytes_per_launch": int(alg), "ms_per_launch": round(phases[dom], 4)}
+    roof["traffic"] = counter_traffic(dom, int(st.tile), int(st.chunk))
     fwd_alg = composite_bytes(Q, P, "composite_fwd")
     fwd_roof = fwd_alg / (phases["composite_fwd"] * 1e-3) / 1e9
+
+    # ---- whole-forward and whole-step HBM fractions (all phases)
+    bins = lv.export_bins(ctx, vox, frame, r.st, r.workspace)
+    M = int(np.count_nonzero(bins["vis"]))
+    del bins
+    b_fwd, b_bwd = step_bytes(scene.n, M, Q, P, int(vox.sh.shape[0]))
+    hbm = {"records": M, "fwd_bytes": int(b_fwd), "bwd_bytes": int(b_bwd),
+           "fwd_frac": round(b_fwd / (fwd_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "step_frac": round((b_fwd + b_bwd) / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    log(f"[bench] whole-path HBM fractions {hbm}")
+
+    # ---- the other workloads
+    others = {}
+    for name in [w for w in args.other_workloads.split(",") if w]:
+        spec = {"grid4k": (False, 0, 0.5), "shell200k": (False, 1, 0.5),
+                "shell200k_train": (False, 1, 0.5), "hemi4m": (True, 0, 0.5)}[name]
+        others[name] = measure_workload(lv, ctx, name, int(st.tile), int(st.chunk),
+                                        max(3, args.steps // 2), 2, *spec)
 
     # ---- CPU baseline: the oracle on a bounded sample (the first views)
     cpu = None
@@ -254,6 +386,8 @@ def main():
         "per_view_ms_batched": round(ms_step / len(cams), 4),
         "single_view_plain_ms": [round(x, 4) for x in single],
         "phases_ms": {k: round(v, 4) for k, v in phases.items()},
+        "whole_path_hbm": hbm,
+        "other_workloads": others,
     }
     print(json.dumps(out), flush=True)
     ctx.close()

@@ -152,9 +152,26 @@ def make_scene_grid(rng: np.random.Generator, res_level: int = 4,
     ijk = np.stack([ix.ravel(), iy.ravel(), iz.ravel()]).astype(np.uint16)
     n = ijk.shape[1]
     level = np.full(n, res_level, dtype=np.uint8)
+    order = octree_order(ijk, level)
+    ijk = np.ascontiguousarray(ijk[:, order])
     density, sh = _draw_params(rng, n, density_std, sh_degree)
     return Scene(root_min=np.array([-0.5, -0.5, -0.5], np.float32), root_size=1.0,
                  ijk=ijk, level=level, density=density, sh=sh, sh_degree=sh_degree)
+
+
+def octree_order(ijk: np.ndarray, level: np.ndarray) -> np.ndarray:
+    """Permutation that puts leaves in octree depth-first order.
+
+    A sparse voxel octree stores its leaves in this order (the order of a
+    depth-first walk, children in z, y, x bit order); it is the storage
+    order of every generated scene.  Key: the bits of the leaf's minimum
+    corner at the finest level, interleaved (x lowest)."""
+    c = [ijk[a].astype(np.int64) << (L_MAX - level.astype(np.int64)) for a in range(3)]
+    key = np.zeros(ijk.shape[1], dtype=np.int64)
+    for b in range(L_MAX):
+        for a in range(3):
+            key |= ((c[a] >> b) & 1) << (3 * b + a)
+    return np.argsort(key, kind="stable")
 
 
 def _key(ix, iy, iz):
@@ -191,7 +208,7 @@ def make_scene_shell(rng: np.random.Generator, n: int, lmin: int, lmax: int,
     direction), or, for a clutter_frac share, uniformly in the root cube.
     Levels are filled coarse to fine; a candidate cell is rejected when it
     duplicates an accepted leaf or lies inside a coarser accepted leaf, so the
-    leaves never overlap.
+    leaves never overlap.  The leaves are returned in octree order.
     """
     assert 0 <= lmin <= lmax <= L_MAX
     root_min = np.array([-1.0, -1.0, -1.0], np.float32)
@@ -242,7 +259,8 @@ def make_scene_shell(rng: np.random.Generator, n: int, lmin: int, lmax: int,
         accepted[l] = got_level
     ijk = np.concatenate(out_ijk, axis=0).T.astype(np.uint16)
     level = np.concatenate(out_lv)
-    perm = rng.permutation(level.shape[0])
+    rng.permutation(level.shape[0])   # keeps the later draws of each seed unchanged
+    perm = octree_order(ijk, level)
     ijk = np.ascontiguousarray(ijk[:, perm])
     level = np.ascontiguousarray(level[perm])
     density, sh = _draw_params(rng, level.shape[0], density_std, sh_degree)

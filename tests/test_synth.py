@@ -55,3 +55,29 @@ def test_named_small_configs():
     assert len(ring) == 8 and all((c.width, c.height) in synth.scenes.RING_RESOLUTIONS for c in ring)
     hemi = synth.make_cameras_hemisphere()
     assert len(hemi) == 16 and all(c.o[1] > 0 for c in hemi)
+
+
+def test_leaves_are_stored_in_octree_order():
+    # depth-first order: a leaf's minimum corner at the finest level, bits
+    # interleaved, never decreases; every ancestor's leaves are contiguous
+    sc = synth.make_scene_shell(np.random.default_rng(9), 3000, 4, 7)
+    fine = [(sc.ijk[a].astype(np.int64) << (synth.scenes.L_MAX - sc.level.astype(np.int64)))
+            for a in range(3)]
+    def morton(v):
+        k = 0
+        for b in range(synth.scenes.L_MAX):
+            for a in range(3):
+                k |= int((fine[a][v] >> b) & 1) << (3 * b + a)
+        return k
+    keys = [morton(v) for v in range(sc.n)]
+    assert all(keys[i] < keys[i + 1] for i in range(sc.n - 1))
+    # leaves under one level-2 cell form one run
+    top = [tuple(int(fine[a][v] >> (synth.scenes.L_MAX - 2)) for a in range(3)) for v in range(sc.n)]
+    seen, prev = set(), None
+    for t in top:
+        if t != prev:
+            assert t not in seen
+            seen.add(t)
+            prev = t
+    g, _, _ = synth.make_config("grid4k")
+    assert g.ijk[:, 1].tolist() == [1, 0, 0] and g.ijk[:, 2].tolist() == [0, 1, 0]
