@@ -55,15 +55,63 @@ hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s) {
   return hipGetLastError();
 }
 
+// ------------------------------------------- block-aggregated tile counts
+// The records of one block (256 consecutive voxels, one view) cover a small
+// window of tiles when the voxels are stored in octree order; a block counts
+// its pairs per tile in LDS and touches each tile's global counter once.
+struct TileWin {
+  uint32_t x0, y0, w, h;
+  bool any;
+};
+
+// Bounding box of the tiles covered by the block's records; every thread of
+// the block must call it (have: the thread's record covers [tx0, tx1] x
+// [ty0, ty1]).
+__device__ TileWin block_tile_window(bool have, uint32_t tx0, uint32_t tx1, uint32_t ty0,
+                                     uint32_t ty1) {
+  __shared__ uint32_t s_r[kBinBlock / 64][4];
+  uint32_t a0 = have ? tx0 : 0xFFFFFFFFu, a1 = have ? tx1 : 0u;
+  uint32_t b0 = have ? ty0 : 0xFFFFFFFFu, b1 = have ? ty1 : 0u;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    a0 = min(a0, uint32_t(__shfl_xor(int(a0), o, 64)));
+    a1 = max(a1, uint32_t(__shfl_xor(int(a1), o, 64)));
+    b0 = min(b0, uint32_t(__shfl_xor(int(b0), o, 64)));
+    b1 = max(b1, uint32_t(__shfl_xor(int(b1), o, 64)));
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) {
+    s_r[w][0] = a0; s_r[w][1] = a1; s_r[w][2] = b0; s_r[w][3] = b1;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kBinBlock / 64; ++k) {
+    a0 = min(a0, s_r[k][0]); a1 = max(a1, s_r[k][1]);
+    b0 = min(b0, s_r[k][2]); b1 = max(b1, s_r[k][3]);
+  }
+  __syncthreads();   // s_r is reused by the next call
+  TileWin win;
+  win.any = a0 <= a1;
+  win.x0 = a0;
+  win.y0 = b0;
+  win.w = win.any ? a1 - a0 + 1u : 0u;
+  win.h = win.any ? b1 - b0 + 1u : 0u;
+  return win;
+}
+
 // ------------------------------------------------------------- preprocess
 // One thread per voxel; the voxel's parameters are read once (coalesced SoA)
 // and every view is processed from registers.
 template <int DEG>
-__global__ __launch_bounds__(256) void k_preprocess(RasterArgs a) {
+__global__ __launch_bounds__(kBinBlock) void k_preprocess(RasterArgs a) {
   constexpr int NB = (DEG + 1) * (DEG + 1);
+  __shared__ uint32_t s_tab[kTileWin];
   const int64_t n = a.n;
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  const int64_t i0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  // threads past the end take part in the block-wide tile counting only
+  const bool valid = i0 < n;
+  const int64_t i = valid ? i0 : n - 1;
+  const uint32_t sub = blockIdx.x & uint32_t(kSpread - 1);
   const int l = a.level[i];
   const float e = ldexpf(a.root_size, -l);
   const uint32_t ix = a.ijk[i], iy = a.ijk[n + i], iz = a.ijk[2 * n + i];
@@ -78,7 +126,7 @@ __global__ __launch_bounds__(256) void k_preprocess(RasterArgs a) {
   vr.be = make_float4(b[0], b[1], b[2], e);
   vr.s0 = make_float4(sg[0], sg[1], sg[2], sg[3]);
   vr.s1 = make_float4(sg[4], sg[5], sg[6], sg[7]);
-  a.ws.vox[i] = vr;
+  if (valid) a.ws.vox[i] = vr;
 
   float k[NB][3];
 #pragma unroll
@@ -189,29 +237,52 @@ __global__ __launch_bounds__(256) void k_preprocess(RasterArgs a) {
       rec.r = fmaxf(col[0], 0.0f);
       rec.g = fmaxf(col[1], 0.0f);
       rec.b = fmaxf(col[2], 0.0f);
-      // --- tile counts
-      const ViewTab vt = a.ws.views[v];
-      const uint32_t tx0 = x0 >> sh_ts, tx1 = x1 >> sh_ts;
-      const uint32_t ty0 = y0 >> sh_ts, ty1 = y1 >> sh_ts;
-      for (uint32_t ty = ty0; ty <= ty1; ++ty)
-        for (uint32_t tx = tx0; tx <= tx1; ++tx)
-          atomicAdd(&a.ws.tcount[uint64_t(i & (kSpread - 1)) * a.T + vt.tile_base + ty * vt.tiles_x + tx], 1u);
     }
-    uint4* dst = reinterpret_cast<uint4*>(&a.ws.rec[size_t(v) * size_t(n) + size_t(i)]);
-    dst[0] = make_uint4(__float_as_uint(rec.r), __float_as_uint(rec.g), __float_as_uint(rec.b),
-                        rec.flags);
-    dst[1] = make_uint4(rec.xr, rec.yr, rec.code_lo, rec.code_hi);
+    // --- tile counts, aggregated over the block
+    const bool have = valid && visible;
+    const uint32_t tx0 = (rec.xr & 0xFFFFu) >> sh_ts, tx1 = (rec.xr >> 16) >> sh_ts;
+    const uint32_t ty0 = (rec.yr & 0xFFFFu) >> sh_ts, ty1 = (rec.yr >> 16) >> sh_ts;
+    const TileWin win = block_tile_window(have, tx0, tx1, ty0, ty1);
+    if (win.any) {
+      const ViewTab vt = a.ws.views[v];
+      uint32_t* tc = a.ws.tcount + uint64_t(sub) * a.T + vt.tile_base;
+      if (uint64_t(win.w) * win.h <= uint64_t(kTileWin)) {
+        const uint32_t nw = win.w * win.h;
+        for (uint32_t k = threadIdx.x; k < nw; k += blockDim.x) s_tab[k] = 0u;
+        __syncthreads();
+        if (have)
+          for (uint32_t ty = ty0; ty <= ty1; ++ty)
+            for (uint32_t tx = tx0; tx <= tx1; ++tx)
+              atomicAdd(&s_tab[(ty - win.y0) * win.w + (tx - win.x0)], 1u);
+        __syncthreads();
+        for (uint32_t k = threadIdx.x; k < nw; k += blockDim.x) {
+          const uint32_t c = s_tab[k];
+          const uint32_t ry = k / win.w;
+          if (c) atomicAdd(&tc[(win.y0 + ry) * vt.tiles_x + win.x0 + (k - ry * win.w)], c);
+        }
+        __syncthreads();   // s_tab is reused by the next view
+      } else if (have) {
+        for (uint32_t ty = ty0; ty <= ty1; ++ty)
+          for (uint32_t tx = tx0; tx <= tx1; ++tx) atomicAdd(&tc[ty * vt.tiles_x + tx], 1u);
+      }
+    }
+    if (valid) {
+      uint4* dst = reinterpret_cast<uint4*>(&a.ws.rec[size_t(v) * size_t(n) + size_t(i)]);
+      dst[0] = make_uint4(__float_as_uint(rec.r), __float_as_uint(rec.g), __float_as_uint(rec.b),
+                          rec.flags);
+      dst[1] = make_uint4(rec.xr, rec.yr, rec.code_lo, rec.code_hi);
+    }
   }
 }
 
 hipError_t launch_preprocess(const RasterArgs& a, hipStream_t s) {
-  const uint32_t blocks = uint32_t((a.n + 255) / 256);
+  const uint32_t blocks = uint32_t((a.n + kBinBlock - 1) / kBinBlock);
   if (blocks == 0) return hipSuccess;
   switch (a.deg) {
-    case 0: hipLaunchKernelGGL(k_preprocess<0>, dim3(blocks), dim3(256), 0, s, a); break;
-    case 1: hipLaunchKernelGGL(k_preprocess<1>, dim3(blocks), dim3(256), 0, s, a); break;
-    case 2: hipLaunchKernelGGL(k_preprocess<2>, dim3(blocks), dim3(256), 0, s, a); break;
-    default: hipLaunchKernelGGL(k_preprocess<3>, dim3(blocks), dim3(256), 0, s, a); break;
+    case 0: hipLaunchKernelGGL(k_preprocess<0>, dim3(blocks), dim3(kBinBlock), 0, s, a); break;
+    case 1: hipLaunchKernelGGL(k_preprocess<1>, dim3(blocks), dim3(kBinBlock), 0, s, a); break;
+    case 2: hipLaunchKernelGGL(k_preprocess<2>, dim3(blocks), dim3(kBinBlock), 0, s, a); break;
+    default: hipLaunchKernelGGL(k_preprocess<3>, dim3(blocks), dim3(kBinBlock), 0, s, a); break;
   }
   return hipGetLastError();
 }
@@ -297,36 +368,78 @@ hipError_t launch_scan_tiles(const RasterArgs& a, uint32_t nblk, hipStream_t s) 
 }
 
 // ------------------------------------------------------------------ emit
-// One thread per (view, voxel) record: writes key = code << 28 | voxel id at
-// tile_start[tile] + slot for every tile the record covers (slots come from
-// an atomic cursor, so the order within a tile is fixed later by the sort).
-__global__ __launch_bounds__(256) void k_emit(RasterArgs a) {
+// One block per (256 voxels, view); each record writes key = code << 28 |
+// voxel id for every tile it covers.  The block counts its pairs per tile in
+// LDS, reserves one range per tile with a single global atomic, and gives
+// each pair a slot in its range with an LDS atomic, so a block's pairs of one
+// tile are written contiguously (their order is fixed later by the sort).
+__global__ __launch_bounds__(kBinBlock) void k_emit(RasterArgs a) {
+  __shared__ uint32_t s_cnt[kTileWin];
+  __shared__ unsigned long long s_base[kTileWin];
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const int v = blockIdx.y;
-  if (i >= a.n) return;
-  const uint4 r1 = reinterpret_cast<const uint4*>(&a.ws.rec[size_t(v) * size_t(a.n) + size_t(i)])[1];
-  const uint32_t flags =
-      reinterpret_cast<const uint4*>(&a.ws.rec[size_t(v) * size_t(a.n) + size_t(i)])[0].w;
-  if (!(flags & 8u)) return;
   const int sh_ts = __builtin_ctz(uint32_t(a.TS));
-  const uint32_t x0 = r1.x & 0xFFFFu, x1 = r1.x >> 16, y0 = r1.y & 0xFFFFu, y1 = r1.y >> 16;
-  const unsigned long long code = (unsigned long long)r1.z | ((unsigned long long)r1.w << 32);
-  const unsigned long long key = (code << kIdBits) | (unsigned long long)i;
-  const ViewTab vt = a.ws.views[v];
-  for (uint32_t ty = (y0 >> sh_ts); ty <= (y1 >> sh_ts); ++ty)
-    for (uint32_t tx = (x0 >> sh_ts); tx <= (x1 >> sh_ts); ++tx) {
-      const uint32_t gt = vt.tile_base + ty * vt.tiles_x + tx;
-      const uint32_t sub = uint32_t(i & (kSpread - 1));
-      const uint32_t slot = atomicAdd(&a.ws.tfill[uint64_t(sub) * a.T + gt], 1u);
-      const uint64_t pos = uint64_t(a.ws.tstart[uint64_t(gt) * kSpread + sub]) + slot;
-      if (pos < a.cap) a.ws.pairs[pos] = key;
+  const uint32_t sub = blockIdx.x & uint32_t(kSpread - 1);
+  bool have = false;
+  uint32_t tx0 = 0, tx1 = 0, ty0 = 0, ty1 = 0;
+  unsigned long long key = 0;
+  if (i < a.n) {
+    const uint4* rp = reinterpret_cast<const uint4*>(&a.ws.rec[size_t(v) * size_t(a.n) + size_t(i)]);
+    const uint32_t flags = rp[0].w;
+    if (flags & 8u) {
+      const uint4 r1 = rp[1];
+      have = true;
+      tx0 = (r1.x & 0xFFFFu) >> sh_ts; tx1 = (r1.x >> 16) >> sh_ts;
+      ty0 = (r1.y & 0xFFFFu) >> sh_ts; ty1 = (r1.y >> 16) >> sh_ts;
+      const unsigned long long code = (unsigned long long)r1.z | ((unsigned long long)r1.w << 32);
+      key = (code << kIdBits) | (unsigned long long)i;
     }
+  }
+  const TileWin win = block_tile_window(have, tx0, tx1, ty0, ty1);
+  if (!win.any) return;   // the whole block
+  const ViewTab vt = a.ws.views[v];
+  uint32_t* fill = a.ws.tfill + uint64_t(sub) * a.T + vt.tile_base;
+  if (uint64_t(win.w) * win.h <= uint64_t(kTileWin)) {
+    const uint32_t nw = win.w * win.h;
+    for (uint32_t k = threadIdx.x; k < nw; k += blockDim.x) s_cnt[k] = 0u;
+    __syncthreads();
+    if (have)
+      for (uint32_t ty = ty0; ty <= ty1; ++ty)
+        for (uint32_t tx = tx0; tx <= tx1; ++tx) atomicAdd(&s_cnt[(ty - win.y0) * win.w + (tx - win.x0)], 1u);
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < nw; k += blockDim.x) {
+      const uint32_t c = s_cnt[k];
+      if (c) {
+        const uint32_t ry = k / win.w;
+        const uint32_t lt = (win.y0 + ry) * vt.tiles_x + win.x0 + (k - ry * win.w);
+        const uint32_t slot = atomicAdd(&fill[lt], c);
+        s_base[k] = (unsigned long long)a.ws.tstart[uint64_t(vt.tile_base + lt) * kSpread + sub] + slot;
+      }
+      s_cnt[k] = 0u;   // now the per-tile cursor of this block
+    }
+    __syncthreads();
+    if (have)
+      for (uint32_t ty = ty0; ty <= ty1; ++ty)
+        for (uint32_t tx = tx0; tx <= tx1; ++tx) {
+          const uint32_t k = (ty - win.y0) * win.w + (tx - win.x0);
+          const unsigned long long pos = s_base[k] + atomicAdd(&s_cnt[k], 1u);
+          if (pos < a.cap) a.ws.pairs[pos] = key;
+        }
+  } else if (have) {
+    for (uint32_t ty = ty0; ty <= ty1; ++ty)
+      for (uint32_t tx = tx0; tx <= tx1; ++tx) {
+        const uint32_t lt = ty * vt.tiles_x + tx;
+        const uint32_t slot = atomicAdd(&fill[lt], 1u);
+        const uint64_t pos = uint64_t(a.ws.tstart[uint64_t(vt.tile_base + lt) * kSpread + sub]) + slot;
+        if (pos < a.cap) a.ws.pairs[pos] = key;
+      }
+  }
 }
 
 hipError_t launch_emit(const RasterArgs& a, hipStream_t s) {
-  const uint32_t bx = uint32_t((a.n + 255) / 256);
+  const uint32_t bx = uint32_t((a.n + kBinBlock - 1) / kBinBlock);
   if (bx == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_emit, dim3(bx, a.V), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_emit, dim3(bx, a.V), dim3(kBinBlock), 0, s, a);
   return hipGetLastError();
 }
 

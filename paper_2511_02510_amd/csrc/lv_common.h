@@ -20,12 +20,16 @@ constexpr float kZNear = 1e-4f;       // binning near plane (camera-space z)
 constexpr int kQueues = 16;
 constexpr int kQueueStride = 32;   // words
 constexpr int kCounterWords = 128 + 2 * kQueues * kQueueStride;
-// Each tile has kSpread pair counters (chosen by voxel id & (kSpread - 1)),
-// stored sub-counter-major so that the atomics on one tile's counters fall on
-// different cache lines; the scan visits them tile-major, so every tile's
-// pairs still form one contiguous segment [tstart[t * kSpread],
-// tstart[(t + 1) * kSpread]).
+// Each tile has kSpread pair counters, stored sub-counter-major; the counter
+// of a (block, tile) is sub = block & (kSpread - 1), where a block is 256
+// consecutive voxels (the preprocess and emit grids both use such blocks).
+// Scanned in tile-major order, so the pairs of a tile still form one
+// contiguous segment [tstart[t * kSpread], tstart[(t + 1) * kSpread]).
 constexpr int kSpread = 16;
+constexpr int kBinBlock = 256;   // voxels per block of preprocess and emit
+// a block counts the tiles its records cover in an LDS table over the
+// block's tile bounding box when that box has at most kTileWin tiles
+constexpr int kTileWin = 2048;
 
 // per-view table built on the device from the cameras (graph-replay safe)
 struct ViewTab {
