@@ -510,18 +510,20 @@ hipError_t launch_order(const RasterArgs& a, hipStream_t s) {
 }
 
 // ------------------------------------------------------------- tile sort
-// One workgroup per tile.  Lists up to kSortCap keys are bitonic-sorted in
-// LDS; longer lists are sorted in kSortCap runs and merged pairwise (each key
-// finds its rank in the partner run by binary search) until one run remains.
-// Keys are unique for non-overlapping leaves, so the order is deterministic.
-// One wave per tile: most lists are a few hundred keys, and a single-wave
-// workgroup synchronises its bitonic stages without cross-wave barriers.
-constexpr int kSortThreads = 64;
+// Tiles are sorted by size class, each class by its own persistent kernel
+// that walks the class's range of the length-ordered tile list (the tile
+// order is built first): lists shorter than 256 keys are bitonic-sorted in
+// 2 KB of LDS by one wave, lists up to kSortCap keys in kSortCap-key LDS by
+// four waves, and longer lists are sorted in kSortCap-key runs and merged
+// pairwise (each key finds its rank in the partner run by binary search)
+// until one run remains.  Keys are unique for non-overlapping leaves, so the
+// order is deterministic.
 
+template <int NT>
 __device__ void lds_bitonic(unsigned long long* sk, uint32_t npow) {
   for (uint32_t k = 2; k <= npow; k <<= 1) {
     for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-      for (uint32_t i = threadIdx.x; i < (npow >> 1); i += kSortThreads) {
+      for (uint32_t i = threadIdx.x; i < (npow >> 1); i += NT) {
         const uint32_t lo = ((i & ~(j - 1)) << 1) | (i & (j - 1));
         const uint32_t hi = lo + j;
         const bool asc = (lo & k) == 0;
@@ -533,80 +535,108 @@ __device__ void lds_bitonic(unsigned long long* sk, uint32_t npow) {
   }
 }
 
-__device__ void sort_run(unsigned long long* sk, const unsigned long long* src,
-                         unsigned long long* dst, uint32_t n) {
+// sorts the n <= CAP keys at src in LDS; writes the sorted keys to dst, or
+// only their voxel ids to ids when dst is null
+template <int NT>
+__device__ void sort_in_lds(unsigned long long* sk, const unsigned long long* src, uint32_t n,
+                            unsigned long long* dst, uint32_t* ids) {
   uint32_t npow = 1;
   while (npow < n) npow <<= 1;
-  for (uint32_t i = threadIdx.x; i < npow; i += kSortThreads) sk[i] = i < n ? src[i] : ~0ull;
+  for (uint32_t i = threadIdx.x; i < npow; i += NT) sk[i] = i < n ? src[i] : ~0ull;
   __syncthreads();
-  lds_bitonic(sk, npow);
-  for (uint32_t i = threadIdx.x; i < n; i += kSortThreads) dst[i] = sk[i];
+  lds_bitonic<NT>(sk, npow);
+  if (dst) {
+    for (uint32_t i = threadIdx.x; i < n; i += NT) dst[i] = sk[i];
+  } else {
+    for (uint32_t i = threadIdx.x; i < n; i += NT) ids[i] = uint32_t(sk[i] & kIdMask);
+  }
   __syncthreads();
 }
 
-__global__ __launch_bounds__(kSortThreads) void k_sort(RasterArgs a) {
+// order positions [p0, p1) of the tiles with length buckets b_lo..b_hi
+// (bucket b holds lengths [2^(b-1), 2^b); buckets are laid out descending)
+__device__ __forceinline__ void class_range(const RasterArgs& a, int b_lo, int b_hi, uint32_t& p0,
+                                            uint32_t& p1) {
+  p0 = a.ws.counters[C_BSTART + b_hi];
+  p1 = a.ws.counters[C_BSTART + b_lo - 1];
+}
+
+template <int CAP, int NT>
+__global__ __launch_bounds__(NT) void k_sort_lds(RasterArgs a, int b_lo, int b_hi) {
+  __shared__ unsigned long long sk[CAP];
+  uint32_t p0, p1;
+  class_range(a, b_lo, b_hi, p0, p1);
+  for (uint32_t p = p0 + blockIdx.x; p < p1; p += gridDim.x) {
+    const uint32_t t = a.ws.torder[p];
+    const uint64_t s0 = tile_begin(a, t);
+    const uint32_t n = uint32_t(tile_begin(a, t + 1) - s0);
+    if (n == 1) {
+      if (threadIdx.x == 0) a.ws.ids[s0] = uint32_t(a.ws.pairs[s0] & kIdMask);
+      continue;
+    }
+    sort_in_lds<NT>(sk, a.ws.pairs + s0, n, nullptr, a.ws.ids + s0);
+  }
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_sort_long(RasterArgs a, int b_lo, int b_hi) {
   __shared__ unsigned long long sk[kSortCap];
-  const uint32_t t = blockIdx.x;
-  const uint64_t s0 = tile_begin(a, t);
-  const uint64_t s1 = tile_begin(a, t + 1);
-  const uint32_t n = uint32_t(s1 - s0);
-  if (n == 0) return;
-  unsigned long long* keys = a.ws.pairs + s0;
-  uint32_t* ids = a.ws.ids + s0;
-  if (n == 1) {
-    if (threadIdx.x == 0) ids[0] = uint32_t(keys[0] & kIdMask);
-    return;
-  }
-  if (n <= uint32_t(kSortCap)) {
-    uint32_t npow = 1;
-    while (npow < n) npow <<= 1;
-    for (uint32_t i = threadIdx.x; i < npow; i += kSortThreads) sk[i] = i < n ? keys[i] : ~0ull;
-    __syncthreads();
-    lds_bitonic(sk, npow);
-    for (uint32_t i = threadIdx.x; i < n; i += kSortThreads) ids[i] = uint32_t(sk[i] & kIdMask);
-    return;
-  }
-  // long list: sorted runs, then pairwise merges between keys and the temp
-  for (uint32_t r0 = 0; r0 < n; r0 += kSortCap) {
-    const uint32_t m = (n - r0) < uint32_t(kSortCap) ? (n - r0) : uint32_t(kSortCap);
-    sort_run(sk, keys + r0, keys + r0, m);
-  }
-  __threadfence_block();
-  __syncthreads();
-  unsigned long long* src = keys;
-  unsigned long long* dst = a.ws.mtmp + s0;
-  for (uint32_t r = kSortCap; r < n; r <<= 1) {
-    for (uint32_t i = threadIdx.x; i < n; i += kSortThreads) {
-      const uint32_t run = i / r;
-      const uint32_t rs = run * r;
-      const uint32_t prt = run ^ 1u;
-      const uint32_t ps = prt * r;
-      const unsigned long long key = src[i];
-      if (ps >= n) { dst[i] = key; continue; }
-      const uint32_t pe = (ps + r) < n ? (ps + r) : n;
-      // rank of key in the partner run: strict for the left run, non-strict
-      // for the right run (keys are unique; this keeps ties stable)
-      uint32_t lo = ps, hi = pe;
-      const bool left = (run & 1u) == 0;
-      while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        const unsigned long long pk = src[mid];
-        const bool go_right = left ? (pk < key) : (pk <= key);
-        if (go_right) lo = mid + 1; else hi = mid;
-      }
-      const uint32_t ms = rs < ps ? rs : ps;
-      dst[ms + (i - rs) + (lo - ps)] = key;
+  uint32_t p0, p1;
+  class_range(a, b_lo, b_hi, p0, p1);
+  for (uint32_t p = p0 + blockIdx.x; p < p1; p += gridDim.x) {
+    const uint32_t t = a.ws.torder[p];
+    const uint64_t s0 = tile_begin(a, t);
+    const uint32_t n = uint32_t(tile_begin(a, t + 1) - s0);
+    unsigned long long* keys = a.ws.pairs + s0;
+    for (uint32_t r0 = 0; r0 < n; r0 += kSortCap) {
+      const uint32_t m = (n - r0) < uint32_t(kSortCap) ? (n - r0) : uint32_t(kSortCap);
+      sort_in_lds<NT>(sk, keys + r0, m, keys + r0, nullptr);
     }
     __threadfence_block();
     __syncthreads();
-    unsigned long long* tmp = src; src = dst; dst = tmp;
+    unsigned long long* src = keys;
+    unsigned long long* dst = a.ws.mtmp + s0;
+    for (uint32_t r = kSortCap; r < n; r <<= 1) {
+      for (uint32_t i = threadIdx.x; i < n; i += NT) {
+        const uint32_t run = i / r;
+        const uint32_t rs = run * r;
+        const uint32_t prt = run ^ 1u;
+        const uint32_t ps = prt * r;
+        const unsigned long long key = src[i];
+        if (ps >= n) { dst[i] = key; continue; }
+        const uint32_t pe = (ps + r) < n ? (ps + r) : n;
+        // rank of key in the partner run: strict for the left run,
+        // non-strict for the right run (keys are unique; this keeps ties
+        // stable)
+        uint32_t lo = ps, hi = pe;
+        const bool left = (run & 1u) == 0;
+        while (lo < hi) {
+          const uint32_t mid = (lo + hi) >> 1;
+          const unsigned long long pk = src[mid];
+          const bool go_right = left ? (pk < key) : (pk <= key);
+          if (go_right) lo = mid + 1; else hi = mid;
+        }
+        const uint32_t ms = rs < ps ? rs : ps;
+        dst[ms + (i - rs) + (lo - ps)] = key;
+      }
+      __threadfence_block();
+      __syncthreads();
+      unsigned long long* tmp = src; src = dst; dst = tmp;
+    }
+    for (uint32_t i = threadIdx.x; i < n; i += NT) a.ws.ids[s0 + i] = uint32_t(src[i] & kIdMask);
+    __syncthreads();
   }
-  for (uint32_t i = threadIdx.x; i < n; i += kSortThreads) ids[i] = uint32_t(src[i] & kIdMask);
 }
 
+// needs the tile order (launch_order) of the same pass
 hipError_t launch_sort(const RasterArgs& a, hipStream_t s) {
   if (a.T == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_sort, dim3(a.T), dim3(kSortThreads), 0, s, a);
+  static_assert(kSortCap == 2048, "size classes assume 2048-key runs");
+  const uint32_t T = a.T;
+  // lengths 1..255: buckets 1..8; 256..2047: buckets 9..11; 2048 and up: 12..31
+  hipLaunchKernelGGL((k_sort_lds<256, 64>), dim3(T < 8192u ? T : 8192u), dim3(64), 0, s, a, 1, 8);
+  hipLaunchKernelGGL((k_sort_lds<kSortCap, 256>), dim3(T < 2048u ? T : 2048u), dim3(256), 0, s, a, 9, 11);
+  hipLaunchKernelGGL((k_sort_long<256>), dim3(T < 512u ? T : 512u), dim3(256), 0, s, a, 12, 31);
   return hipGetLastError();
 }
 

@@ -282,12 +282,12 @@ lv_status lv_forward(lv_context* ctx, const lv_voxels* vox, const lv_frame* fram
     LV_TRY(lv::launch_emit(a, stream), "emit");
   }
   {
-    PhaseTimer t(ctx, LV_PH_SORT, stream);
-    LV_TRY(lv::launch_sort(a, stream), "sort");
-  }
-  {
     PhaseTimer t(ctx, LV_PH_ORDER, stream);
     LV_TRY(lv::launch_order(a, stream), "order");
+  }
+  {
+    PhaseTimer t(ctx, LV_PH_SORT, stream);
+    LV_TRY(lv::launch_sort(a, stream), "sort");
   }
   {
     PhaseTimer t(ctx, LV_PH_COMPOSITE_FWD, stream);
