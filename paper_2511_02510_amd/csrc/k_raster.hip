@@ -38,7 +38,7 @@ struct Stage {
   float col[3][CH];
   uint32_t xr[CH];    // pixel-centre range x0 | x1 << 16
   uint32_t yr[CH];
-  uint32_t id[CH];
+  uint32_t id[CH];    // voxel id | colour clamp mask (bit c: raw channel c > 0) << 28
 };
 
 struct Ray {
@@ -100,7 +100,7 @@ __device__ __forceinline__ void stage_chunk(Stage<CH>& S, const RasterArgs& a, c
       S.col[2][k] = __uint_as_float(r0.z);
       S.xr[k] = r1.x;
       S.yr[k] = r1.y;
-      S.id[k] = id;
+      S.id[k] = id | ((r0.w & 7u) << kIdBits);
     } else {
       S.xr[k] = 1u;   // empty range (x0 = 1 > x1 = 0)
       S.yr[k] = 1u;
@@ -376,7 +376,7 @@ __global__ __launch_bounds__(TS* TS) void k_composite_fwd(RasterArgs a) {
       __syncthreads();
       for (uint32_t k = threadIdx.x; k < nc; k += NT) {
         const uint32_t u = s_wmax[k];
-        if (u) atomicMax(reinterpret_cast<unsigned int*>(a.wmax) + S.id[k], u);
+        if (u) atomicMax(reinterpret_cast<unsigned int*>(a.wmax) + (S.id[k] & kIdMask), u);
       }
       if (__syncthreads_and(st.done ? 1 : 0)) break;
     }
@@ -577,8 +577,10 @@ __global__ __launch_bounds__(TS* TS) void k_composite_bwd(RasterArgs a) {
       for (uint32_t e = threadIdx.x; e < 11u * nc; e += NT) {
         const uint32_t k = e / 11u, c = e - 11u * k;
         const float s = float(s_g[c][k]);
-        if (s != 0.0f) {
-          const size_t id = S.id[k];
+        // colour gradients stop at the clamp (channels whose raw value <= 0)
+        const bool pass = c < 8u || ((S.id[k] >> (kIdBits + (c - 8u))) & 1u);
+        if (s != 0.0f && pass) {
+          const size_t id = S.id[k] & kIdMask;
           float* dst = c < 8u ? &a.ws.dden[8 * id + c]
                               : &a.ws.dcol[(size_t(v) * size_t(a.n) + id) * 3 + (c - 8u)];
           unsafeAtomicAdd(dst, s);

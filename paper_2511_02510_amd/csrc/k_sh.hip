@@ -1,9 +1,9 @@
-// Backward tail: colour gradients of every (view, voxel) record are taken
-// through the clamp at zero and the SH expansion to the SH coefficients,
-// summed over views, and the voxel-major corner-density gradient the
-// composite pass accumulated is transposed into the caller's [8][n] rows.
-// One thread per voxel; the output rows are written coalesced and fully
-// overwritten.
+// Backward tail: colour gradients of every (view, voxel) record (already
+// stopped at the clamp at zero by the composite pass) are taken through the
+// SH expansion to the SH coefficients, summed over views, and the
+// voxel-major corner-density gradient the composite pass accumulated is
+// transposed into the caller's [8][n] rows.  One thread per voxel; the
+// output rows are written coalesced and fully overwritten.
 #include "lv_common.h"
 
 namespace lv {
@@ -36,13 +36,10 @@ __global__ __launch_bounds__(256) void k_sh_bwd(RasterArgs a) {
   const float he = 0.5f * vr.be.w;
   const float xv0 = vr.be.x + he, xv1 = vr.be.y + he, xv2 = vr.be.z + he;
   for (int v = 0; v < a.V; ++v) {
-    const size_t r = size_t(v) * size_t(n) + size_t(i);
-    const uint32_t flags = a.ws.rec[r].flags;
-    if (!(flags & 8u)) continue;
-    const float* dcp = a.ws.dcol + 3 * r;
-    const float g0 = (flags & 1u) ? dcp[0] : 0.0f;
-    const float g1 = (flags & 2u) ? dcp[1] : 0.0f;
-    const float g2 = (flags & 4u) ? dcp[2] : 0.0f;
+    // the composite backward zeroed the clamped channels (and never wrote
+    // the records of views that do not see the voxel)
+    const float* dcp = a.ws.dcol + 3 * (size_t(v) * size_t(n) + size_t(i));
+    const float g0 = dcp[0], g1 = dcp[1], g2 = dcp[2];
     if (g0 == 0.0f && g1 == 0.0f && g2 == 0.0f) continue;
     const lv_camera& cam = a.cams[v];
     float dx = xv0 - cam.o[0], dy = xv1 - cam.o[1], dz = xv2 - cam.o[2];
