@@ -405,10 +405,12 @@ __global__ __launch_bounds__(TS* TS) void k_composite_fwd(RasterArgs a) {
 // T_{k-1} = T_k exp(tau_k), starting from the transmittance saved before the
 // last hit, so no per-sample state is stored.
 //
-// Accumulation: the 11 contributions of a fragment are summed over runs of
-// lanes on the same voxel (seg_reduce_rows), added to the voxel's LDS
-// accumulator by the run's last lane, and each chunk is flushed with one
-// global atomic per (voxel, component).
+// Accumulation: the sweep queues each hit (voxel, pixel, dL/dtau, weight,
+// chord) in a per-wave LDS ring; 64 queued hits at a time are expanded by
+// the whole wave into their 11 contributions, summed over runs of lanes on
+// the same voxel (seg_reduce_rows) and added to the voxel's LDS accumulator
+// by the run's last lane; each chunk is flushed with one global atomic per
+// (voxel, component).
 struct BwdState {
   float Tb;            // transmittance before the hit processed last
   float gC0, gC1, gC2, gD, gA;
@@ -416,10 +418,14 @@ struct BwdState {
   bool first;
 };
 
-// one fragment; writes the 11 gradient contributions into g, returns hit
+// Sequential part of one fragment (this lane's pixel, voxel jj), in the
+// pixel's back-to-front sweep: transmittance, weight and dL/dtau.  Returns
+// hit and, for a hit, what the deferred part needs: gh = dL/dtau * half
+// chord, the weight wk and the chord's midpoint and half length.
 template <int CH>
-__device__ __forceinline__ bool bwd_fragment(const Stage<CH>& S, int jj, const Ray& ray,
-                                             BwdState& st, const float bg[3], float g[11]) {
+__device__ __forceinline__ bool bwd_sweep(const Stage<CH>& S, int jj, const Ray& ray, BwdState& st,
+                                          const float bg[3], float& gh, float& wk, float& tm,
+                                          float& hl) {
   const Seg sg = slab(S, jj, ray);
   if (!sg.hit) return false;
   const Quad q = quad(S, jj, ray, sg);
@@ -435,22 +441,49 @@ __device__ __forceinline__ bool bwd_fragment(const Stage<CH>& S, int jj, const R
     Tafter = st.Tb;
     Tbefore = st.Tb * __expf(q.tau);
   }
-  const float wk = Tbefore * al;
+  wk = Tbefore * al;
   const float c0 = S.col[0][jj], c1 = S.col[1][jj], c2 = S.col[2][jj];
   float dtau = st.base + st.gD * (Tafter * q.tm - st.SD);
   dtau = fmaf(st.gC0, Tafter * c0 - st.SC0, dtau);
   dtau = fmaf(st.gC1, Tafter * c1 - st.SC1, dtau);
   dtau = fmaf(st.gC2, Tafter * c2 - st.SC2, dtau);
-  const float gh = dtau * q.hl;
+  gh = dtau * q.hl;
+  tm = q.tm;
+  hl = q.hl;
+  st.SC0 = fmaf(wk, c0, st.SC0);
+  st.SC1 = fmaf(wk, c1, st.SC1);
+  st.SC2 = fmaf(wk, c2, st.SC2);
+  st.SD = fmaf(wk, q.tm, st.SD);
+  st.Tb = Tbefore;
+  return true;
+}
+
+// Deferred part of a fragment: the 8 corner-density contributions (gh times
+// the trilinear corner weights summed over the two Gauss points, recomputed
+// from the chord exactly as the sweep computed them) and the 3 colour
+// contributions wk * dL/dC.
+template <int CH>
+__device__ __forceinline__ void bwd_spread(const Stage<CH>& S, int jj, const float d[3], float gh,
+                                           float wk, const float gc[3], float tm, float hl,
+                                           float g[11]) {
+  const float ta = fmaf(-hl, kGL, tm), tb = fmaf(hl, kGL, tm);
+  const float ie = S.inve[jj];
+  float ua[3], ub[3];
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    const float du = d[ax] * ie;
+    ua[ax] = fmaf(ta, du, -S.su[ax][jj]);
+    ub[ax] = fmaf(tb, du, -S.su[ax][jj]);
+  }
   {
-    const float x1 = q.ua[0], y1 = q.ua[1], z1 = q.ua[2];
+    const float x1 = ua[0], y1 = ua[1], z1 = ua[2];
     const float x0 = 1.0f - x1, y0 = 1.0f - y1, z0 = 1.0f - z1;
     const float y0z0 = y0 * z0, y1z0 = y1 * z0, y0z1 = y0 * z1, y1z1 = y1 * z1;
     g[0] = x0 * y0z0; g[1] = x1 * y0z0; g[2] = x0 * y1z0; g[3] = x1 * y1z0;
     g[4] = x0 * y0z1; g[5] = x1 * y0z1; g[6] = x0 * y1z1; g[7] = x1 * y1z1;
   }
   {
-    const float x1 = q.ub[0], y1 = q.ub[1], z1 = q.ub[2];
+    const float x1 = ub[0], y1 = ub[1], z1 = ub[2];
     const float x0 = 1.0f - x1, y0 = 1.0f - y1, z0 = 1.0f - z1;
     const float y0z0 = y0 * z0, y1z0 = y1 * z0, y0z1 = y0 * z1, y1z1 = y1 * z1;
     g[0] = gh * (g[0] + x0 * y0z0); g[1] = gh * (g[1] + x1 * y0z0);
@@ -458,15 +491,51 @@ __device__ __forceinline__ bool bwd_fragment(const Stage<CH>& S, int jj, const R
     g[4] = gh * (g[4] + x0 * y0z1); g[5] = gh * (g[5] + x1 * y0z1);
     g[6] = gh * (g[6] + x0 * y1z1); g[7] = gh * (g[7] + x1 * y1z1);
   }
-  g[8] = wk * st.gC0;
-  g[9] = wk * st.gC1;
-  g[10] = wk * st.gC2;
-  st.SC0 = fmaf(wk, c0, st.SC0);
-  st.SC1 = fmaf(wk, c1, st.SC1);
-  st.SC2 = fmaf(wk, c2, st.SC2);
-  st.SD = fmaf(wk, q.tm, st.SD);
-  st.Tb = Tbefore;
-  return true;
+  g[8] = wk * gc[0];
+  g[9] = wk * gc[1];
+  g[10] = wk * gc[2];
+}
+
+// Per-wave ring of deferred fragments (kRing entries; the sweep appends at
+// most 64 per step and the wave drains 64 whenever that many are queued, so
+// fewer than kRing are ever pending).
+constexpr int kRing = 128;
+
+template <int CH>
+struct BwdRing {
+  uint32_t key[kRing];   // jj | pixel lane << 16
+  float gh[kRing], wk[kRing], tm[kRing], hl[kRing];
+  float d[64][3];        // unit ray direction of each pixel of the wave
+  float gc[64][3];       // dL/dC of each pixel of the wave
+};
+
+// Processes the `count` (<= 64) oldest entries of the ring with one entry per
+// lane: corner and colour contributions, summed over runs of lanes on the
+// same voxel, added to the chunk's LDS accumulators.  Every lane of the
+// wave must call it.
+template <int CH>
+__device__ __forceinline__ void bwd_drain(const Stage<CH>& S, const BwdRing<CH>& R,
+                                          double (*s_g)[CH], uint32_t head, uint32_t count) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const bool valid = lane < count;
+  int jj = 0;
+  float g[11];
+#pragma unroll
+  for (int c = 0; c < 11; ++c) g[c] = 0.0f;
+  if (valid) {
+    const uint32_t e = (head + lane) & uint32_t(kRing - 1);
+    const uint32_t key = R.key[e];
+    const uint32_t p = key >> 16;
+    jj = int(key & 0xFFFFu);
+    const float d[3] = {R.d[p][0], R.d[p][1], R.d[p][2]};
+    const float gc[3] = {R.gc[p][0], R.gc[p][1], R.gc[p][2]};
+    bwd_spread(S, jj, d, R.gh[e], R.wk[e], gc, R.tm[e], R.hl[e], g);
+  }
+  const bool last = seg_reduce_rows<11>(g, jj, valid);
+  if (valid && last) {
+#pragma unroll
+    for (int c = 0; c < 11; ++c) atomicAdd(&s_g[c][jj], double(g[c]));
+  }
 }
 
 template <int TS, int NW>
@@ -477,9 +546,11 @@ __global__ __launch_bounds__(TS* TS) void k_composite_bwd(RasterArgs a) {
   __shared__ Stage<CH> S;
   __shared__ Masks<TS, CH> MK;
   __shared__ double s_g[11][CH];
+  __shared__ BwdRing<CH> s_ring[NT / 64];
   __shared__ uint32_t s_tile, s_maxn;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lx = pix_x_of_lane(lane), ly = pix_y_of_lane(lane);
+  BwdRing<CH>& ring = s_ring[wave];
   const int wbx = (wave % BPR) * 8, wby = (wave / BPR) * 8;
   const float bg[3] = {a.bg[0], a.bg[1], a.bg[2]};
 
@@ -525,11 +596,15 @@ __global__ __launch_bounds__(TS* TS) void k_composite_bwd(RasterArgs a) {
       st.gD = a.d_depth ? a.d_depth[gp] : 0.0f;
       st.gA = a.d_alpha ? a.d_alpha[gp] : 0.0f;
     }
+    // the wave's rays and colour gradients, read back by the deferred part
+    ring.d[lane][0] = ray.d[0]; ring.d[lane][1] = ray.d[1]; ring.d[lane][2] = ray.d[2];
+    ring.gc[lane][0] = st.gC0; ring.gc[lane][1] = st.gC1; ring.gc[lane][2] = st.gC2;
     if (nlast) atomicMax(&s_maxn, nlast);
     __syncthreads();
     const uint32_t maxn = s_maxn;
     __syncthreads();
 
+    uint32_t rhead = 0u, rcount = 0u;   // the wave's ring (wave-uniform)
     const int nch = int((maxn + CH - 1) / CH);
     for (int ci = nch - 1; ci >= 0; --ci) {
       const uint32_t cb = uint32_t(ci) * CH;
@@ -549,27 +624,46 @@ __global__ __launch_bounds__(TS* TS) void k_composite_bwd(RasterArgs a) {
         const int lim = int(nlast) - int(cb) - w * 64;
         if (lim <= 0) m = 0;
         else if (lim < 64) m &= (1ull << lim) - 1ull;
-        // wave-uniform loop: each lane takes its next candidate (back to front)
+        // wave-uniform loop: each lane takes its next candidate (back to
+        // front); hits are queued in the wave's ring in lane order, and the
+        // wave drains 64 of them whenever that many are pending
         for (;;) {
           const bool act = m != 0;
           if (__ballot(act) == 0) break;
-          int jj = -1;
           bool hit = false;
-          float g[11];
-#pragma unroll
-          for (int c = 0; c < 11; ++c) g[c] = 0.0f;
+          int jj = 0;
+          float gh = 0.0f, wk = 0.0f, tm = 0.0f, hl = 0.0f;
           if (act) {
             const int jbit = 63 - __builtin_clzll(m);
             m &= ~(1ull << jbit);
             jj = w * 64 + jbit;
-            hit = bwd_fragment(S, jj, ray, st, bg, g);
+            hit = bwd_sweep(S, jj, ray, st, bg, gh, wk, tm, hl);
           }
-          const bool last = seg_reduce_rows<11>(g, jj, hit);
-          if (hit && last) {
-#pragma unroll
-            for (int c = 0; c < 11; ++c) atomicAdd(&s_g[c][jj], double(g[c]));
+          const unsigned long long hb = __ballot(hit);
+          if (hb) {
+            if (hit) {
+              const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+                  uint32_t(hb >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(hb), 0u));
+              const uint32_t e = (rhead + rcount + below) & uint32_t(kRing - 1);
+              ring.key[e] = uint32_t(jj) | (uint32_t(lane) << 16);
+              ring.gh[e] = gh;
+              ring.wk[e] = wk;
+              ring.tm[e] = tm;
+              ring.hl[e] = hl;
+            }
+            rcount += uint32_t(__popcll(hb));
+            if (rcount >= 64u) {
+              bwd_drain(S, ring, s_g, rhead, 64u);
+              rhead = (rhead + 64u) & uint32_t(kRing - 1);
+              rcount -= 64u;
+            }
           }
         }
+      }
+      if (rcount) {   // the rest of this chunk's fragments
+        bwd_drain(S, ring, s_g, rhead, rcount);
+        rhead = (rhead + rcount) & uint32_t(kRing - 1);
+        rcount = 0u;
       }
       __syncthreads();
       // flush: consecutive lanes take consecutive components of a voxel, so
