@@ -55,25 +55,51 @@ def composite_source_hash():
     return h.hexdigest()[:16]
 
 
-def counter_traffic(kernel, tile, chunk):
-    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE/WRITE_SIZE
-    summary, or None when it was taken on other kernel sources or settings."""
+VALU_MD = os.path.join(ROOT, "profiles", "composite_valu_ring1m.md")
+VALU_PEAK = 256 * 4 * 2.4e9 / 4   # wave64 VALU instructions/s: 16-lane SIMDs, 4 per CU
+
+
+def _profile_lines(path, tile, chunk):
+    """Machine-readable lines of a committed counter summary, keyed by their
+    first two fields, or None when the summary was taken on other composite
+    sources or settings."""
     try:
-        with open(PROFILE_MD) as fh:
+        with open(path) as fh:
             text = fh.read()
     except OSError:
         return None
     vals = {}
     for line in text.splitlines():
         f = line.split()
-        if len(f) >= 2 and f[0] in ("traffic_bytes_per_launch", "composite_source_sha256_16", "settings"):
-            vals[(f[0], f[1] if f[0] == "traffic_bytes_per_launch" else "")] = f[1:]
-    if vals.get(("composite_source_sha256_16", ""), [None])[0] != composite_source_hash():
+        if len(f) >= 2:
+            vals[(f[0], f[1])] = f[1:]
+    if ("composite_source_sha256_16", composite_source_hash()) not in vals:
         return None
-    if vals.get(("settings", ""), []) != [f"tile={tile}", f"chunk={chunk}"]:
+    if ("settings", f"tile={tile}") not in vals or vals[("settings", f"tile={tile}")] != \
+            [f"tile={tile}", f"chunk={chunk}"]:
         return None
-    t = vals.get(("traffic_bytes_per_launch", "k_" + kernel))
+    return vals
+
+
+def counter_traffic(kernel, tile, chunk):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE/WRITE_SIZE
+    summary, or None when it was taken on other kernel sources or settings."""
+    vals = _profile_lines(PROFILE_MD, tile, chunk)
+    t = vals.get(("traffic_bytes_per_launch", "k_" + kernel)) if vals else None
     return int(float(t[1])) if t else None
+
+
+def counter_valu(kernel, tile, chunk, ms):
+    """VALU issue of `kernel` from the committed counter summary: wave
+    instructions per launch, issue rate over the launch time measured here
+    against the chip's peak, and lane utilisation; None when stale."""
+    vals = _profile_lines(VALU_MD, tile, chunk)
+    t = vals.get(("valu_instr_per_launch", "k_" + kernel)) if vals else None
+    if not t:
+        return None
+    inst = float(t[1])
+    return {"wave_instr_per_launch": int(inst), "issue_frac": round(inst / (ms * 1e-3) / VALU_PEAK, 4),
+            "peak_wave_instr_per_s": VALU_PEAK, "lane_util": float(t[3])}
 
 
 # SURVEY-style algorithmic bytes of the whole forward and backward (all
@@ -329,6 +355,7 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
             "alg_bytes_per_launch": int(alg), "ms_per_launch": round(phases[dom], 4)}
     roof["traffic"] = counter_traffic(dom, int(st.tile), int(st.chunk))
+    roof["valu"] = counter_valu(dom, int(st.tile), int(st.chunk), phases[dom])
     fwd_alg = composite_bytes(Q, P, "composite_fwd")
     fwd_roof = fwd_alg / (phases["composite_fwd"] * 1e-3) / 1e9
 
