@@ -59,47 +59,42 @@ VALU_MD = os.path.join(ROOT, "profiles", "composite_valu_ring1m.md")
 VALU_PEAK = 256 * 4 * 2.4e9 / 4   # wave64 VALU instructions/s: 16-lane SIMDs, 4 per CU
 
 
-def _profile_lines(path, tile, chunk):
-    """Machine-readable lines of a committed counter summary, keyed by their
-    first two fields, or None when the summary was taken on other composite
-    sources or settings."""
+def _profile_lines(path, name, kernel, tile, chunk):
+    """Fields after `<name> <kernel>` of the committed counter summary line
+    for these settings, or None (no such line, or the summary was taken on
+    other composite kernel sources)."""
     try:
         with open(path) as fh:
             text = fh.read()
     except OSError:
         return None
-    vals = {}
+    ok, found = False, None
     for line in text.splitlines():
         f = line.split()
-        if len(f) >= 2:
-            vals[(f[0], f[1])] = f[1:]
-    if ("composite_source_sha256_16", composite_source_hash()) not in vals:
-        return None
-    if ("settings", f"tile={tile}") not in vals or vals[("settings", f"tile={tile}")] != \
-            [f"tile={tile}", f"chunk={chunk}"]:
-        return None
-    return vals
+        if f[:2] == ["composite_source_sha256_16", composite_source_hash()]:
+            ok = True
+        if len(f) >= 5 and f[0] == name and f[1] == kernel and f[3:5] == [f"tile={tile}", f"chunk={chunk}"]:
+            found = f[2:]
+    return found if ok else None
 
 
 def counter_traffic(kernel, tile, chunk):
     """HBM bytes per launch of `kernel` from the committed FETCH_SIZE/WRITE_SIZE
     summary, or None when it was taken on other kernel sources or settings."""
-    vals = _profile_lines(PROFILE_MD, tile, chunk)
-    t = vals.get(("traffic_bytes_per_launch", "k_" + kernel)) if vals else None
-    return int(float(t[1])) if t else None
+    t = _profile_lines(PROFILE_MD, "traffic_bytes_per_launch", "k_" + kernel, tile, chunk)
+    return int(float(t[0])) if t else None
 
 
 def counter_valu(kernel, tile, chunk, ms):
     """VALU issue of `kernel` from the committed counter summary: wave
     instructions per launch, issue rate over the launch time measured here
     against the chip's peak, and lane utilisation; None when stale."""
-    vals = _profile_lines(VALU_MD, tile, chunk)
-    t = vals.get(("valu_instr_per_launch", "k_" + kernel)) if vals else None
+    t = _profile_lines(VALU_MD, "valu_instr_per_launch", "k_" + kernel, tile, chunk)
     if not t:
         return None
-    inst = float(t[1])
+    inst = float(t[0])
     return {"wave_instr_per_launch": int(inst), "issue_frac": round(inst / (ms * 1e-3) / VALU_PEAK, 4),
-            "peak_wave_instr_per_s": VALU_PEAK, "lane_util": float(t[3])}
+            "peak_wave_instr_per_s": VALU_PEAK, "lane_util": float(t[4])}
 
 
 # SURVEY-style algorithmic bytes of the whole forward and backward (all
