@@ -128,6 +128,48 @@ def test_depth_quantile_degenerate_inputs(ctx):
     assert np.array_equal(prune.cpu().numpy(), ref["prune"])
 
 
+@pytest.mark.parametrize("n_bins,q", [(1, 0.1), (64, 0.1), (16, 1.0), (5, 0.5)])
+def test_depth_quantile_bin_counts_and_ranks(ctx, n_bins, q):
+    # one bin (a plain quantile), the largest bin count the entry point takes,
+    # the maximum rank (q = 1), and an odd bin count; random w_max with ties
+    import paper_2511_02510_amd as lv
+    import torch
+    scene = small_shell(30000, seed=31, lmin=5, lmax=9, clutter=0.1)
+    cams = [look_at((2.2, 0.8, 1.1), 40, 30), look_at((-1.7, 1.3, 1.9), 30, 40)]
+    rng = np.random.default_rng(32)
+    wm = np.round(rng.random(scene.n) ** 2, 3).astype(np.float32)
+    say(f"depth quantile: {n_bins} bins, q = {q}")
+    vox = lv.Voxels.from_scene(scene, ctx.device)
+    frame = lv.Frame(cams, ctx.device)
+    ws = torch.empty(lv.quantile_workspace_size(vox.n, n_bins), dtype=torch.uint8, device=ctx.device)
+    tau = torch.empty(n_bins, device=ctx.device)
+    prune = torch.empty(vox.n, dtype=torch.uint8, device=ctx.device)
+    bins = torch.empty(vox.n, dtype=torch.uint8, device=ctx.device)
+    for _ in range(2):   # the second call reuses the workspace as it was left
+        lv.depth_quantile(ctx, vox, frame, to_dev(wm, ctx.device), n_bins, q, ws, tau, prune, bins)
+    torch.cuda.synchronize()
+    ref = oquant.depth_quantile(scene, cams, wm, n_bins, q)
+    assert np.array_equal(bins.cpu().numpy(), ref["bins"])
+    assert np.array_equal(tau.cpu().numpy(), ref["tau"])
+    assert np.array_equal(prune.cpu().numpy(), ref["prune"])
+
+
+def test_depth_quantile_without_voxels(ctx):
+    import paper_2511_02510_amd as lv
+    import torch
+    say("depth quantile: no voxels")
+    scene = synth.scene_subset(small_shell(1000, seed=33, lmin=4, lmax=6), np.arange(0))
+    cams = [look_at((2.0, 1.0, 1.5), 16, 16)]
+    vox = lv.Voxels.from_scene(scene, ctx.device)
+    frame = lv.Frame(cams, ctx.device)
+    ws = torch.empty(max(lv.quantile_workspace_size(0, 16), 1), dtype=torch.uint8, device=ctx.device)
+    tau = torch.zeros(16, device=ctx.device)
+    prune = torch.empty(1, dtype=torch.uint8, device=ctx.device)
+    lv.depth_quantile(ctx, vox, frame, torch.empty(1, device=ctx.device), 16, 0.1, ws, tau, prune)
+    torch.cuda.synchronize()
+    assert np.all(np.isneginf(tau.cpu().numpy()))
+
+
 def test_autograd_function_matches_direct_calls(ctx):
     import paper_2511_02510_amd as lv
     import torch
