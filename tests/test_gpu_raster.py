@@ -183,3 +183,30 @@ def test_backward_rgb_only_and_deterministic_forward(ctx):
     assert rel_l2(g1["dd"], g2["dd"]) < 1e-6
     dd, dsh = oracle.backward(scene, cams, grads[0])
     assert rel_l2(g1["dd"], dd) <= GRAD_TOL and rel_l2(g1["dsh"], dsh) <= GRAD_TOL
+
+
+def test_many_uneven_views_forward_backward_and_keys(ctx):
+    # 40 views of odd sizes around the scene in one call: view lookup of every
+    # tile, per-view tile and pixel offsets, and the interleaved tile queues
+    # over many more tiles than queues
+    scene = small_shell(6000, seed=41, lmin=4, lmax=7, clutter=0.2)
+    rng = np.random.default_rng(42)
+    cams = []
+    for i in range(40):
+        # generic directions: no camera on a coordinate plane, so no pixel ray
+        # runs inside a voxel face (a measure-zero case the FP32 path and the
+        # FP64 oracle may resolve to different sides)
+        az, el = 2 * np.pi * i / 40 + 0.137, 0.6 * np.sin(1.7 * i) + 0.071
+        o = 2.4 * np.array([np.cos(el) * np.cos(az), np.sin(el), np.cos(el) * np.sin(az)])
+        cams.append(look_at(tuple(o), int(rng.integers(5, 41)), int(rng.integers(3, 37))))
+    say("forward + backward, 40 uneven views")
+    P = sum(c.npix for c in cams)
+    grads = random_grads(np.random.default_rng(43), P)
+    for tile in (8, 16):
+        g = run_gpu(ctx, scene, cams, tile=tile, chunk=64, grads=grads)
+        check_keys(g["bins"], scene, cams, tile)
+        ref = oracle.render(scene, cams)
+        check_images(g, ref)
+        assert np.abs(g["wmax"] - ref["wmax"]).max() <= WMAX_TOL
+        dd, dsh = oracle.backward(scene, cams, *grads)
+        assert rel_l2(g["dd"], dd) <= GRAD_TOL and rel_l2(g["dsh"], dsh) <= GRAD_TOL
