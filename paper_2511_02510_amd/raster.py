@@ -256,14 +256,49 @@ def graph_reset(ctx):
     ctx.check(ctx.lib.lv_graph_reset(ctx.h), "lv_graph_reset")
 
 
-def autotune(ctx, vox, frame, reps=3, t_eps=1e-6, stream=None):
-    """-> (best LvSettings, ms table [3 tiles x 3 chunks])."""
+def tune_key(vox, frame) -> str:
+    """Workload class an autotuning result is reused for: voxel count rounded
+    to a power of two, view count, the multiset of resolutions, SH degree."""
+    n = int(vox.n)
+    bucket = n.bit_length() if n > 0 else 0
+    res = ",".join(f"{w}x{h}" for w, h in sorted(frame.sizes))
+    return f"n2^{bucket}|v{frame.n_views}|{res}|sh{int(vox.sh_degree)}"
+
+
+def autotune(ctx, vox, frame, reps=3, t_eps=1e-6, stream=None, cache=None):
+    """-> (best LvSettings, ms table [3 tiles x 3 chunks]).
+
+    cache: optional path of a JSON file of earlier results keyed by tune_key;
+    a hit returns the stored tile and chunk (pair capacity 0: the Renderer
+    plans it) without timing anything, a miss times and stores."""
+    import json
+    import os
+    key = tune_key(vox, frame)
+    if cache is not None and os.path.exists(cache):
+        with open(cache) as fh:
+            known = json.load(fh)
+        if key in known:
+            hit = known[key]
+            return (settings(tile=int(hit["tile"]), chunk=int(hit["chunk"]), t_eps=t_eps),
+                    np.array(hit["ms_table"], dtype=np.float64).reshape(3, 3))
     best = settings(t_eps=t_eps)
     table = (ctypes.c_float * 9)()
     ctx.check(ctx.lib.lv_autotune(ctx.h, ctypes.byref(vox.struct), ctypes.byref(frame.struct),
                                   int(reps), ctypes.byref(best), ctypes.cast(table, ctypes.c_void_p),
                                   _stream(stream)), "lv_autotune")
-    return best, np.array(list(table), dtype=np.float64).reshape(3, 3)
+    ms = np.array(list(table), dtype=np.float64).reshape(3, 3)
+    if cache is not None:
+        known = {}
+        if os.path.exists(cache):
+            with open(cache) as fh:
+                known = json.load(fh)
+        known[key] = {"tile": int(best.tile), "chunk": int(best.chunk),
+                      "ms_table": [round(float(x), 4) for x in ms.ravel()]}
+        tmp = f"{cache}.tmp{os.getpid()}"
+        with open(tmp, "w") as fh:
+            json.dump(known, fh, indent=1, sort_keys=True)
+        os.replace(tmp, cache)
+    return best, ms
 
 
 def set_timing(ctx, enable: bool):

@@ -136,3 +136,24 @@ def test_gamma_schedule_matches_eq9(t):
     lib = _abi.lib()
     got = lib.lv_gamma_schedule(t, 20000, 0.3, 0.6, 0.6)
     assert abs(got - oracle_loss.gamma_schedule(t, 20000)) < 1e-6
+
+
+def test_autotune_cache_key_and_hit_without_device(tmp_path):
+    # a cached result is returned without touching the device (ctx unused)
+    import json
+    import paper_2511_02510_amd as lv
+    import synth
+    from synth.scenes import look_at
+    scene = synth.scene_subset(synth.make_config("grid4k")[0], np.arange(1000))
+    cams = [look_at((2.0, 1.0, 1.5), 64, 48), look_at((1.0, 2.0, -1.5), 32, 32)]
+    vox = lv.Voxels.from_scene(scene, "cpu")
+    frame = lv.Frame(cams, "cpu")
+    key = lv.tune_key(vox, frame)
+    assert key == "n2^10|v2|32x32,64x48|sh0"
+    # the resolution multiset, not the view order, is part of the key
+    assert lv.tune_key(vox, lv.Frame(cams[::-1], "cpu")) == key
+    path = tmp_path / "tune.json"
+    path.write_text(json.dumps({key: {"tile": 8, "chunk": 128, "ms_table": list(range(9))}}))
+    best, table = lv.autotune(None, vox, frame, cache=str(path))
+    assert (best.tile, best.chunk, best.pair_capacity) == (8, 128, 0)
+    assert table.shape == (3, 3) and table[2, 2] == 8

@@ -265,14 +265,18 @@ def test_graph_replays_match_eager(ctx):
     assert np.abs(got[0].cpu().numpy() - ref["rgb"]).max() <= IMG_TOL
 
 
-def test_autotune_returns_a_runnable_setting(ctx):
+def test_autotune_returns_a_runnable_setting(ctx, tmp_path):
     import paper_2511_02510_amd as lv
     scene = small_shell(20000, seed=28, lmin=5, lmax=9)
     cams = [look_at((2.1, 0.5, 1.0), 160, 120)]
     say("autotune")
     vox = lv.Voxels.from_scene(scene, ctx.device)
     frame = lv.Frame(cams, ctx.device)
-    best, table = lv.autotune(ctx, vox, frame, reps=2)
+    cache = str(tmp_path / "tune.json")
+    best, table = lv.autotune(ctx, vox, frame, reps=2, cache=cache)
+    again, table2 = lv.autotune(ctx, vox, frame, reps=2, cache=cache)   # served by the cache
+    assert (again.tile, again.chunk) == (best.tile, best.chunk)
+    assert np.allclose(table2, np.round(table, 4))
     assert best.tile in (8, 16, 32) and best.chunk in (64, 128, 256)
     assert np.all(table > 0)
     assert abs(table.min() - table[[8, 16, 32].index(best.tile), [64, 128, 256].index(best.chunk)]) < 1e-9
