@@ -384,11 +384,29 @@ def main():
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         tc = time.perf_counter()
         oracle.render(scene, sub, threads=threads)
+        t_fwd = time.perf_counter() - tc
         oracle.backward(scene, sub, g, threads=threads)
         dt = time.perf_counter() - tc
+        # one thread on an evenly spread 1/16 of the same pixels
+        pix1 = np.arange(0, Ps, 16)
+        t1 = time.perf_counter()
+        oracle.render(scene, sub, pix_list=pix1, threads=1)
+        oracle.backward(scene, sub, g, pix_list=pix1, threads=1)   # gradient of the listed pixels
+        dt1 = time.perf_counter() - t1
+        cpu_model = ""
+        try:
+            with open("/proc/cpuinfo") as fh:
+                cpu_model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+        except OSError:
+            pass
         cpu = {"value": round(Ps / dt / 1e6, 4), "unit": "MP/s", "cores": threads, "kind": "oracle",
                "sample": f"fwd+bwd of view(s) 0..{nv - 1} ({Ps} px) of the same workload, FP64, "
-                         f"{dt:.1f} s"}
+                         f"{dt:.1f} s",
+               "fwd_value": round(Ps / t_fwd / 1e6, 4),
+               "one_thread_value": round(pix1.shape[0] / dt1 / 1e6, 4),
+               "one_thread_sample": f"fwd+bwd of every 16th pixel of the same views ({pix1.shape[0]} px), "
+                                    f"{dt1:.1f} s",
+               "cpu_model": cpu_model, "host_threads": os.cpu_count()}
         log(f"[bench] oracle {cpu}")
 
     out = {
