@@ -13,23 +13,43 @@
 namespace lv {
 
 // ------------------------------------------------------------------ setup
+// Split-plane threshold of the eye along one axis.  The split planes of every
+// level lie on the finest grid: the plane of fine index k (an odd multiple of
+// 2^(kLMax - m) at level m) is root_min + 2^-kLMax fl(k root_size) in binary32,
+// which is exactly how the per-level plane root_min + fl((2p + 1) root_size
+// 2^-m) rounds, since scaling by a power of two is exact.  These values are
+// non-decreasing in k, so "the eye lies above the plane" holds exactly for
+// k <= the threshold found here by bisection: the largest k in [0, 2^kLMax)
+// with o > plane(k), or -1 if there is none.
+__device__ int32_t split_threshold(float o, float root_min, float root_size) {
+  int32_t lo = -1, hi = (1 << kLMax) - 1;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) >> 1;
+    const float plane = root_min + ldexpf(float(mid) * root_size, -kLMax);
+    if (o > plane) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
 __global__ void k_setup(RasterArgs a) {
   const int t = threadIdx.x;
   for (int k = t; k < kCounterWords; k += blockDim.x) a.ws.counters[k] = 0u;
+  for (int v = t; v < a.V; v += blockDim.x)
+    for (int ax = 0; ax < 3; ++ax)
+      a.ws.views[v].cell[ax] = split_threshold(a.cams[v].o[ax], a.root_min[ax], a.root_size);
   if (t == 0) {
     uint32_t tb = 0;
     uint64_t pb = 0;
     for (int v = 0; v < a.V; ++v) {
       const int W = a.cams[v].width, H = a.cams[v].height;
-      ViewTab vt;
+      ViewTab& vt = a.ws.views[v];   // field by field: the other lanes write cell[]
       vt.tile_base = tb;
       vt.tiles_x = uint32_t((W + a.TS - 1) / a.TS);
       vt.tiles_y = uint32_t((H + a.TS - 1) / a.TS);
       vt.W = W;
       vt.H = H;
-      vt.pad = 0;
       vt.pix_base = pb;
-      a.ws.views[v] = vt;
       tb += vt.tiles_x * vt.tiles_y;
       pb += uint64_t(W) * uint64_t(H);
     }
@@ -113,6 +133,30 @@ __device__ TileWin block_tile_window(bool have, uint32_t tx0, uint32_t tx1, uint
 // ------------------------------------------------------------- preprocess
 // One thread per voxel; the voxel's parameters are read once (coalesced SoA)
 // and every view is processed from registers.
+// Flipped path of a level-l cell index x along one axis, given the eye's
+// split-plane threshold c: bit (l - m) is the level-m child bit XOR whether
+// the eye lies above that level's split plane.  While the cell and the eye's
+// fine index share their top levels the flip equals the eye's own bit, so
+// those path bits are 0; at the first level where they differ the bit is 1;
+// below it the eye lies entirely on one side, so the flip is constant (1 when
+// the eye's index is the larger).  c = -1: the eye lies below every plane.
+__device__ __forceinline__ uint32_t flipped_path(uint32_t x, int l, int32_t c) {
+  if (c < 0) return x;
+  const uint32_t cc = uint32_t(c) >> (kLMax - l);
+  const uint32_t diff = x ^ cc;
+  if (diff == 0u) return 0u;
+  const uint32_t top = 1u << (31 - __builtin_clz(diff));
+  return top | ((cc > x ? ~x : x) & (top - 1u));
+}
+
+// bits 0..5 of x to bits 0, 3, ..., 15
+__device__ __forceinline__ uint32_t spread3_6(uint32_t x) {
+  x = (x | (x << 8)) & 0x0000F00Fu;
+  x = (x | (x << 4)) & 0x000C30C3u;
+  x = (x | (x << 2)) & 0x00249249u;
+  return x;
+}
+
 template <int DEG>
 __global__ __launch_bounds__(kBinBlock) void k_preprocess(RasterArgs a) {
   constexpr int NB = (DEG + 1) * (DEG + 1);
@@ -206,24 +250,13 @@ __global__ __launch_bounds__(kBinBlock) void k_preprocess(RasterArgs a) {
       rec.xr = x0 | (x1 << 16);
       rec.yr = y0 | (y1 << 16);
       // --- visibility code: flipped octree path, 3 bits per level
-      uint64_t code = 0;
-      const uint32_t idx3[3] = {ix, iy, iz};
-      const float oo[3] = {o0, o1, o2};
-      for (int m = 1; m <= l; ++m) {
-        const float half = ldexpf(a.root_size, -m);
-        uint32_t bits = 0;
-#pragma unroll
-        for (int ax = 0; ax < 3; ++ax) {
-          const uint32_t id_m = idx3[ax] >> (l - m);
-          const uint32_t child = id_m & 1u;
-          const uint32_t parent = id_m >> 1;
-          float plane = float(2u * parent + 1u) * half;
-          plane = a.root_min[ax] + plane;
-          const uint32_t flip = oo[ax] > plane ? 1u : 0u;
-          bits |= (child ^ flip) << ax;
-        }
-        code |= uint64_t(bits) << (3 * (kLMax - m));
-      }
+      const int32_t* cell = a.ws.views[v].cell;
+      const uint32_t fpx = flipped_path(ix, l, cell[0]);
+      const uint32_t fpy = flipped_path(iy, l, cell[1]);
+      const uint32_t fpz = flipped_path(iz, l, cell[2]);
+      const uint32_t lo = spread3_6(fpx & 63u) | (spread3_6(fpy & 63u) << 1) | (spread3_6(fpz & 63u) << 2);
+      const uint32_t hi = spread3_6(fpx >> 6) | (spread3_6(fpy >> 6) << 1) | (spread3_6(fpz >> 6) << 2);
+      const uint64_t code = (uint64_t(lo) | (uint64_t(hi) << 18)) << (3 * (kLMax - l));
       rec.code_lo = uint32_t(code);
       rec.code_hi = uint32_t(code >> 32);
       // --- colour: SH at the direction camera -> voxel centre

@@ -38,7 +38,7 @@ struct ViewTab {
   uint32_t tiles_y;
   int32_t W;
   int32_t H;
-  uint32_t pad;
+  int32_t cell[3];     // split-plane threshold of the eye per axis (see split_threshold)
   uint64_t pix_base;   // first global pixel index of the view
 };
 

@@ -51,6 +51,34 @@ def test_keys_camera_inside_root_cube(ctx):
     assert np.any(full & (vis[0] == 1))
 
 
+def test_keys_eye_on_split_planes(ctx):
+    # the visibility code behind the front-to-back order of eq. 2-4 compares
+    # the eye with the split plane of every level: eyes exactly on planes of
+    # levels 1, 3, 9 and 12, one ulp above and below them, and outside the
+    # root cube on either side, with a root cube whose size is not a power of
+    # two and leaves down to level 12
+    scene = small_shell(20000, seed=6, lmin=5, lmax=12, clutter=0.3)
+    scene.root_min = np.array([-1.3, -1.05, -1.7], np.float32)
+    scene.root_size = 2.7
+    f32 = np.float32
+
+    def plane(a, k):
+        return f32(scene.root_min[a] + f32(np.ldexp(f32(f32(k) * f32(scene.root_size)), -12)))
+
+    on = np.array([plane(0, 2048), plane(1, 1536), plane(2, 1237)], np.float32)
+    up = np.nextafter(on, np.float32(np.inf))
+    down = np.nextafter(on, np.float32(-np.inf))
+    outside = np.array([scene.root_min[0] - 0.5, scene.root_min[1] + 2.7 + 0.3, plane(2, 3000)],
+                       np.float32)
+    centre = scene.root_min.astype(np.float64) + 1.35
+    cams = [look_at(o.astype(np.float64), 320, 240, target=tuple(centre + [0.31, -0.17, 0.23]))
+            for o in (on, up, down, outside)]
+    say("keys with the eye on split planes, 4 views, leaves to level 12")
+    g = run_gpu(ctx, scene, cams, tile=16)
+    check_keys(g["bins"], scene, cams, 16)
+    assert int(scene.level.max()) == 12
+
+
 def test_keys_long_tile_lists_use_merge_path(ctx):
     # 32^3 uniform grid seen small: single tiles hold more than 4096 voxels
     rng = np.random.default_rng(3)
