@@ -21,23 +21,23 @@ constexpr int kSumSlots = 32;
 constexpr int kSumStride = 16;   // doubles
 
 struct LossWS {
-  uint32_t* hist;    // [V][256]
-  SelState* st;      // [V]
+  SelSet sel;        // one selection per view: hist [4][V][256], st [2][V]
   double* sums;      // [V][kSumSlots][kSumStride]
 };
 
 uint64_t loss_ws_bytes(int V) {
-  return align256(size_t(V) * 256 * 4) + align256(size_t(V) * sizeof(SelState)) +
+  return align256(size_t(4) * V * 256 * 4) + align256(size_t(2) * V * sizeof(SelState)) +
          align256(size_t(V) * kSumSlots * kSumStride * 8);
 }
 
 static LossWS loss_bind(void* base, int V) {
   char* b = static_cast<char*>(base);
   LossWS w;
-  w.hist = reinterpret_cast<uint32_t*>(b);
-  b += align256(size_t(V) * 256 * 4);
-  w.st = reinterpret_cast<SelState*>(b);
-  b += align256(size_t(V) * sizeof(SelState));
+  w.sel.nseg = V;
+  w.sel.hist = reinterpret_cast<uint32_t*>(b);
+  b += align256(size_t(4) * V * 256 * 4);
+  w.sel.st = reinterpret_cast<SelState*>(b);
+  b += align256(size_t(2) * V * sizeof(SelState));
   w.sums = reinterpret_cast<double*>(b);
   return w;
 }
@@ -51,17 +51,18 @@ __device__ __forceinline__ uint64_t view_offset(const lv_camera* cams, int v) {
 __global__ void k_loss_setup(const lv_camera* cams, int V, LossWS w, double q) {
   const int v = blockIdx.x;
   const uint64_t P = uint64_t(cams[v].width) * uint64_t(cams[v].height);
-  w.hist[size_t(v) * 256 + threadIdx.x] = 0u;
+  for (int pass = 0; pass < 4; ++pass) sel_hist(w.sel, pass, v)[threadIdx.x] = 0u;
   if (threadIdx.x < kSumSlots) w.sums[(size_t(v) * kSumSlots + threadIdx.x) * kSumStride] = 0.0;
   if (threadIdx.x == 0) {
     double r = ceil(q * double(P));
     if (r < 1.0) r = 1.0;
     if (r > double(P)) r = double(P);
-    w.st[v].prefix = 0u;
-    w.st[v].k = P > 0 ? uint32_t(r) - 1u : 0u;
-    w.st[v].n = uint32_t(P);
-    w.st[v].valid = P > 0 ? 1u : 0u;
-
+    SelState st;
+    st.prefix = 0u;
+    st.k = P > 0 ? uint32_t(r) - 1u : 0u;
+    st.n = uint32_t(P);
+    st.valid = P > 0 ? 1u : 0u;
+    w.sel.st[v] = st;
   }
 }
 
@@ -114,11 +115,19 @@ __global__ __launch_bounds__(256) void k_sobel(const lv_camera* cams, const floa
 __global__ __launch_bounds__(256) void k_hist_views(const lv_camera* cams, const float* vals,
                                                     LossWS w, int pass) {
   __shared__ uint32_t lh[kHistCopies * kHistStride];
+  __shared__ SelState s_st;
   const int v = blockIdx.y;
   for (int k = threadIdx.x; k < kHistCopies * kHistStride; k += 256) lh[k] = 0u;
+  if (threadIdx.x < 64) {
+    const SelState t = sel_state(w.sel, v, pass);
+    if (threadIdx.x == 0) {
+      s_st = t;
+      if (blockIdx.x == 0 && pass > 0) sel_store(w.sel, v, pass, t);
+    }
+  }
   __syncthreads();
   uint32_t* mine = lh + (threadIdx.x & (kHistCopies - 1)) * kHistStride;
-  const SelState st = w.st[v];
+  const SelState st = s_st;
   const uint64_t npv = uint64_t(cams[v].width) * uint64_t(cams[v].height);
   const uint64_t off = view_offset(cams, v);
   const int sh = sel_shift(pass);
@@ -145,42 +154,7 @@ __global__ __launch_bounds__(256) void k_hist_views(const lv_camera* cams, const
   uint32_t c = 0;
 #pragma unroll
   for (int i = 0; i < kHistCopies; ++i) c += lh[i * kHistStride + threadIdx.x];
-  if (c) atomicAdd(&w.hist[size_t(v) * 256 + threadIdx.x], c);
-}
-
-__global__ __launch_bounds__(256) void k_sel_step(SelState* st, uint32_t* hist, int nseg, int pass) {
-  const int sg = int(blockIdx.x) * 4 + int(threadIdx.x >> 6);
-  if (sg >= nseg) return;
-  const int lane = threadIdx.x & 63;
-  SelState* S = st + sg;
-  uint32_t* h = hist + size_t(sg) * 256 + 4 * lane;
-  const uint4 c4 = *reinterpret_cast<const uint4*>(h);
-  const uint32_t c[4] = {c4.x, c4.y, c4.z, c4.w};
-  const uint32_t tot = (c[0] + c[1]) + (c[2] + c[3]);
-  uint32_t incl = tot;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t y = __shfl_up(incl, o, 64);
-    if (lane >= o) incl += y;
-  }
-  const uint32_t excl = incl - tot;
-  const uint32_t k = S->k;
-  if (S->valid != 0 && excl <= k && k < incl) {   // the one lane whose bins hold rank k
-    uint32_t e = excl, d = 0;
-#pragma unroll
-    for (uint32_t j = 0; j < 3; ++j) {
-      if (d == j && k >= e + c[j]) { e += c[j]; d = j + 1; }
-    }
-    S->prefix = S->prefix | ((4u * uint32_t(lane) + d) << sel_shift(pass));
-    S->k = k - e;
-  }
-  *reinterpret_cast<uint4*>(h) = make_uint4(0u, 0u, 0u, 0u);
-}
-
-hipError_t launch_sel_step(SelState* st, uint32_t* hist, int nseg, int pass, hipStream_t s) {
-  if (nseg <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_sel_step, dim3((nseg + 3) / 4), dim3(256), 0, s, st, hist, nseg, pass);
-  return hipGetLastError();
+  if (c) atomicAdd(&sel_hist(w.sel, pass, v)[threadIdx.x], c);
 }
 
 // b^gamma for b > 0 through the hardware log2 / exp2 (relative error a few
@@ -192,10 +166,16 @@ __device__ __forceinline__ float pow_pos(float b, float gamma) {
 __global__ __launch_bounds__(256) void k_lf_weight(const lv_camera* cams, float* wbuf, LossWS w,
                                                    float gamma, int form, float eps) {
   __shared__ double s_part[4];
+  __shared__ uint32_t s_key;
   const int v = blockIdx.y;
   const uint32_t np32 = uint32_t(cams[v].width) * uint32_t(cams[v].height);
   float* wv = wbuf + view_offset(cams, v);
-  const float g99 = key2f(w.st[v].prefix);
+  if (threadIdx.x < 64) {   // the 99th percentile: the last pass's digit
+    const SelState t = sel_state(w.sel, v, 4);
+    if (threadIdx.x == 0) s_key = t.prefix;
+  }
+  __syncthreads();
+  const float g99 = key2f(s_key);
   double part = 0.0;
   constexpr int U = 4;
   const uint32_t step = gridDim.x * (256u * U);
@@ -272,11 +252,8 @@ hipError_t run_lf_weight(const lv_camera* cams_dev, const lv_camera* cams_host, 
   hipLaunchKernelGGL(k_sobel, dim3(uint32_t(max_sobel_blocks), V), dim3(256), 0, s, cams_dev, target,
                      weight);
   const dim3 hgrid(hist_blocks_for(max_pix), V);
-  for (int pass = 0; pass < 4; ++pass) {
+  for (int pass = 0; pass < 4; ++pass)
     hipLaunchKernelGGL(k_hist_views, hgrid, dim3(256), 0, s, cams_dev, (const float*)weight, w, pass);
-    const hipError_t e = launch_sel_step(w.st, w.hist, V, pass, s);
-    if (e != hipSuccess) return e;
-  }
   hipLaunchKernelGGL(k_lf_weight, grid, dim3(256), 0, s, cams_dev, weight, w, gamma, form, eps);
   hipLaunchKernelGGL(k_lf_norm, grid, dim3(256), 0, s, cams_dev, weight, w);
   return hipGetLastError();

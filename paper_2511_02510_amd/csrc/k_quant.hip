@@ -18,14 +18,26 @@ struct QuantWS {
   uint32_t* dkey;     // [n] keys of delta
   uint32_t* wkey;     // [n] keys of w_max
   uint8_t* bins;      // [n]
-  uint32_t* hist;     // [2 + B][256]
-  SelState* st;       // [2 + B]: p5, p95, bins
+  SelSet pct;         // p5 and p95 of delta (2 segments)
+  SelSet bin;         // the quantile of w_max in each bin (B segments)
   uint32_t* cnt;      // [B]
 };
 
+static size_t sel_bytes(int nseg) {
+  return align256(size_t(4) * nseg * 1024) + align256(size_t(2) * nseg * sizeof(SelState));
+}
+
 uint64_t quant_ws_bytes(int64_t n, int B) {
-  return align256(4 * size_t(n)) * 2 + align256(size_t(n)) + align256(size_t(2 + B) * 1024) +
-         align256(size_t(2 + B) * sizeof(SelState)) + align256(4 * size_t(B));
+  return align256(4 * size_t(n)) * 2 + align256(size_t(n)) + sel_bytes(2) + sel_bytes(B) +
+         align256(4 * size_t(B));
+}
+
+static char* sel_bind(char* b, int nseg, SelSet& S) {
+  S.nseg = nseg;
+  S.hist = reinterpret_cast<uint32_t*>(b);
+  b += align256(size_t(4) * nseg * 1024);
+  S.st = reinterpret_cast<SelState*>(b);
+  return b + align256(size_t(2) * nseg * sizeof(SelState));
 }
 
 static QuantWS quant_bind(void* base, int64_t n, int B) {
@@ -34,8 +46,8 @@ static QuantWS quant_bind(void* base, int64_t n, int B) {
   w.dkey = reinterpret_cast<uint32_t*>(b); b += align256(4 * size_t(n));
   w.wkey = reinterpret_cast<uint32_t*>(b); b += align256(4 * size_t(n));
   w.bins = reinterpret_cast<uint8_t*>(b); b += align256(size_t(n));
-  w.hist = reinterpret_cast<uint32_t*>(b); b += align256(size_t(2 + B) * 1024);
-  w.st = reinterpret_cast<SelState*>(b); b += align256(size_t(2 + B) * sizeof(SelState));
+  b = sel_bind(b, 2, w.pct);
+  b = sel_bind(b, B, w.bin);
   w.cnt = reinterpret_cast<uint32_t*>(b);
   return w;
 }
@@ -50,15 +62,23 @@ __device__ __forceinline__ uint32_t rank_of(double q, uint32_t n) {
   return uint32_t(r) - 1u;
 }
 
+// block s < 2: percentile segment s; block 2 + b: bin b (its initial state
+// comes from the bin counts, in the first histogram pass; until then both
+// rows say "no answer", which is also the result when there are no voxels)
 __global__ void k_q_setup(QuantWS w, int B, uint32_t n) {
-  const int s = blockIdx.x;   // segment
-  w.hist[size_t(s) * 256 + threadIdx.x] = 0u;
+  const int s = blockIdx.x;
+  const SelSet& S = s < 2 ? w.pct : w.bin;
+  const int sg = s < 2 ? s : s - 2;
+  for (int pass = 0; pass < 4; ++pass) sel_hist(S, pass, sg)[threadIdx.x] = 0u;
   if (threadIdx.x == 0) {
-    w.st[s].prefix = 0u;
-    w.st[s].n = s < 2 ? n : 0u;
-    w.st[s].valid = (s < 2 && n > 0) ? 1u : 0u;
-    w.st[s].k = s == 0 ? rank_of(0.05, n) : (s == 1 ? rank_of(0.95, n) : 0u);
-    if (s >= 2) w.cnt[s - 2] = 0u;
+    SelState st;
+    st.prefix = 0u;
+    st.n = s < 2 ? n : 0u;
+    st.valid = (s < 2 && n > 0) ? 1u : 0u;
+    st.k = s == 0 ? rank_of(0.05, n) : (s == 1 ? rank_of(0.95, n) : 0u);
+    sel_store(S, sg, 0, st);
+    sel_store(S, sg, 1, st);
+    if (s >= 2) w.cnt[sg] = 0u;
   }
 }
 
@@ -84,23 +104,38 @@ __global__ __launch_bounds__(256) void k_q_delta(RasterArgs a, QuantWS w) {
   w.wkey[i] = f2key(a.wmax[i]);
 }
 
-// Histogram of the current digit.  dual: every element counts towards
-// segments seg0 and seg0 + 1 (p5 and p95 of the same keys); otherwise the
-// element's segment is seg0 + label (label 0 when labels is null).  The
-// block counts into ncopy padded lane-indexed copies of its nseg x 256 bins.
+// Histogram of the current digit for the selections of S.  dual: every
+// element counts towards segments 0 and 1 (p5 and p95 of the same keys);
+// otherwise the element's segment is its label.  With cnt (pass 0 of the
+// per-bin selection) the initial states are the ranks ceil(q |V_b|) of the
+// bin counts.  The block counts into ncopy padded lane-indexed copies of its
+// nseg x 256 bins.
 __global__ __launch_bounds__(256) void k_q_hist(const uint32_t* keys, const uint8_t* labels, int64_t n,
-                                                QuantWS w, int seg0, int nseg, int pass, int dual,
-                                                int ncopy) {
+                                                SelSet S, int pass, int dual, int ncopy,
+                                                const uint32_t* cnt, double q) {
   extern __shared__ uint32_t lh[];
+  const int nseg = S.nseg;
   const int stride = nseg * 256 + (ncopy > 1 ? 1 : 0);
   for (int k = threadIdx.x; k < ncopy * stride; k += 256) lh[k] = 0u;
-  __syncthreads();
   uint32_t* mine = lh + (threadIdx.x & (ncopy - 1)) * stride;
   // segment states in LDS (a binned element looks its segment up by label)
-  __shared__ uint32_t s_pre[2 + kMaxBins], s_ok[2 + kMaxBins];
-  for (int k = threadIdx.x; k < nseg; k += 256) {
-    s_pre[k] = w.st[seg0 + k].prefix;
-    s_ok[k] = w.st[seg0 + k].valid;
+  __shared__ uint32_t s_pre[kMaxBins], s_ok[kMaxBins];
+  for (int sg = int(threadIdx.x >> 6); sg < nseg; sg += int(blockDim.x >> 6)) {
+    SelState st;
+    if (cnt) {
+      const uint32_t c = cnt[sg];
+      st.prefix = 0u;
+      st.n = c;
+      st.valid = c > 0 ? 1u : 0u;
+      st.k = c > 0 ? rank_of(q, c) : 0u;
+    } else {
+      st = sel_state(S, sg, pass);
+    }
+    if ((threadIdx.x & 63) == 0) {
+      s_pre[sg] = st.prefix;
+      s_ok[sg] = st.valid;
+      if (blockIdx.x == 0 && (pass > 0 || cnt)) sel_store(S, sg, pass, st);
+    }
   }
   __syncthreads();
   const int sh = sel_shift(pass);
@@ -135,16 +170,22 @@ __global__ __launch_bounds__(256) void k_q_hist(const uint32_t* keys, const uint
   for (int k = threadIdx.x; k < nseg * 256; k += 256) {
     uint32_t c = 0;
     for (int i = 0; i < ncopy; ++i) c += lh[i * stride + k];
-    if (c) atomicAdd(&w.hist[size_t(seg0) * 256 + k], c);
+    if (c) atomicAdd(&sel_hist(S, pass, 0)[k], c);
   }
 }
 
 // bins from delta and (p5, p95), with the per-bin counts
 __global__ __launch_bounds__(256) void k_q_bins(int64_t n, int B, QuantWS w, uint8_t* out_bins) {
   extern __shared__ uint32_t lc[];
+  __shared__ uint32_t s_key[2];
   for (int k = threadIdx.x; k < B; k += 256) lc[k] = 0u;
+  if (threadIdx.x < 128) {   // p5 and p95: the last pass's digits
+    const int sg = int(threadIdx.x >> 6);
+    const SelState st = sel_state(w.pct, sg, 4);
+    if ((threadIdx.x & 63) == 0) s_key[sg] = st.prefix;
+  }
   __syncthreads();
-  const float p5 = key2f(w.st[0].prefix), p95 = key2f(w.st[1].prefix);
+  const float p5 = key2f(s_key[0]), p95 = key2f(s_key[1]);
   const bool spread = isfinite(p95) && p95 > p5;
   const float den = p95 - p5;
   for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
@@ -169,29 +210,19 @@ __global__ __launch_bounds__(256) void k_q_bins(int64_t n, int B, QuantWS w, uin
     if (lc[k]) atomicAdd(&w.cnt[k], lc[k]);
 }
 
-// per-bin selection state from the bin counts
-__global__ void k_q_ranks(int B, double q, QuantWS w) {
-  const int b = threadIdx.x;
-  if (b >= B) return;
-  const uint32_t c = w.cnt[b];
-  SelState& st = w.st[2 + b];
-  st.prefix = 0u;
-  st.n = c;
-  st.valid = c > 0 ? 1u : 0u;
-  st.k = c > 0 ? rank_of(q, c) : 0u;
-}
-
+// tau_b from the last pass's digits (-inf for an empty bin), then the prune
+// mask over a grid-stride loop
 __global__ __launch_bounds__(256) void k_q_prune(int64_t n, int B, QuantWS w, const float* wmax,
                                                  float* tau, uint8_t* prune) {
-  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
-  if (blockIdx.x == 0 && threadIdx.x < B) {
-    const SelState st = w.st[2 + threadIdx.x];
-    tau[threadIdx.x] = st.valid ? key2f(st.prefix) : -INFINITY;
+  __shared__ float s_tau[kMaxBins];
+  for (int sg = int(threadIdx.x >> 6); sg < B; sg += int(blockDim.x >> 6)) {
+    const SelState st = sel_state(w.bin, sg, 4);
+    if ((threadIdx.x & 63) == 0) s_tau[sg] = st.valid ? key2f(st.prefix) : -INFINITY;
   }
-  if (i >= n) return;
-  const SelState st = w.st[2 + w.bins[i]];
-  const float t = st.valid ? key2f(st.prefix) : -INFINITY;
-  prune[i] = wmax[i] <= t ? 1u : 0u;
+  __syncthreads();
+  if (blockIdx.x == 0 && threadIdx.x < B) tau[threadIdx.x] = s_tau[threadIdx.x];
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256)
+    prune[i] = wmax[i] <= s_tau[w.bins[i]] ? 1u : 0u;
 }
 
 // histogram copies: as many as fit in 64 KB of LDS, at most 16
@@ -221,25 +252,18 @@ hipError_t run_depth_quantile(const RasterArgs& a, int B, double q, void* ws, fl
     hipLaunchKernelGGL(k_q_delta, dim3(uint32_t((a.n + 255) / 256)), dim3(256), 0, s, a, w);
     const uint32_t g = grid_for(a.n);
     // p5 and p95 of delta: segments 0 and 1 over every voxel, in the same passes
-    for (int pass = 0; pass < 4; ++pass) {
+    for (int pass = 0; pass < 4; ++pass)
       hipLaunchKernelGGL(k_q_hist, dim3(g), dim3(256), hist_lds(2, kCopiesDual), s,
-                         (const uint32_t*)w.dkey, (const uint8_t*)nullptr, a.n, w, 0, 2, pass, 1,
-                         kCopiesDual);
-      const hipError_t e = launch_sel_step(w.st, w.hist, 2, pass, s);
-      if (e != hipSuccess) return e;
-    }
+                         (const uint32_t*)w.dkey, (const uint8_t*)nullptr, a.n, w.pct, pass, 1,
+                         kCopiesDual, (const uint32_t*)nullptr, q);
     hipLaunchKernelGGL(k_q_bins, dim3(g), dim3(256), B * 4, s, a.n, B, w, out_bins);
-    hipLaunchKernelGGL(k_q_ranks, dim3(1), dim3(64), 0, s, B, q, w);
     const int cb = binned_copies(B);
-    for (int pass = 0; pass < 4; ++pass) {
+    for (int pass = 0; pass < 4; ++pass)
       hipLaunchKernelGGL(k_q_hist, dim3(g), dim3(256), hist_lds(B, cb), s, (const uint32_t*)w.wkey,
-                         (const uint8_t*)w.bins, a.n, w, 2, B, pass, 0, cb);
-      const hipError_t e = launch_sel_step(w.st + 2, w.hist + 2 * 256, B, pass, s);
-      if (e != hipSuccess) return e;
-    }
+                         (const uint8_t*)w.bins, a.n, w.bin, pass, 0, cb,
+                         pass == 0 ? (const uint32_t*)w.cnt : (const uint32_t*)nullptr, q);
   }
-  hipLaunchKernelGGL(k_q_prune, dim3(uint32_t((a.n + 255) / 256) > 0 ? uint32_t((a.n + 255) / 256) : 1u),
-                     dim3(256), 0, s, a.n, B, w, a.wmax, tau, prune);
+  hipLaunchKernelGGL(k_q_prune, dim3(grid_for(a.n)), dim3(256), 0, s, a.n, B, w, a.wmax, tau, prune);
   return hipGetLastError();
 }
 

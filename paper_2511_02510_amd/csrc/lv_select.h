@@ -37,12 +37,75 @@ __device__ __forceinline__ uint32_t sel_himask(int pass) {
   return pass == 0 ? 0u : (0xFFFFFFFFu << (sel_shift(pass) + 8));
 }
 
-// Digit choice of one pass for segments [0, nseg) after a histogram kernel
-// has counted the current digit of every key that matches its segment's
-// prefix (a separate launch, so the counts are complete and visible): one
-// wave per segment, each lane holding 4 consecutive bins.  The wave scans the
-// bin counts, keeps the digit whose cumulative count passes k, lowers k by
-// the counts before it, and clears the bins for the next pass.
-hipError_t launch_sel_step(SelState* st, uint32_t* hist, int nseg, int pass, hipStream_t s);
+// nseg simultaneous selections.  hist[4][nseg][256] holds the digit counts
+// of each pass (zero before its pass); st[2][nseg] holds each segment's state
+// after an even (row 0) or odd (row 1) number of passes.  There is no
+// separate digit-choice launch: the launch that needs the state before pass p
+// (pass p's histogram, or the consumer with p = 4) chooses pass p-1's digit
+// itself from that pass's complete histogram, every block redundantly, and
+// block 0 stores the result in row p & 1 for the next launch.  It reads row
+// (p-1) & 1, so no block reads a state while another overwrites it.
+struct SelSet {
+  SelState* st;
+  uint32_t* hist;
+  int nseg;
+};
+
+__device__ __forceinline__ uint32_t* sel_hist(const SelSet& S, int pass, int sg) {
+  return S.hist + (size_t(pass) * size_t(S.nseg) + size_t(sg)) * 256;
+}
+
+// Digit choice of one pass for one segment, by one full wave (each lane
+// holds 4 consecutive bins): the digit whose cumulative count passes k joins
+// the prefix and k drops by the counts before it.  A segment with no answer
+// is returned unchanged.
+__device__ __forceinline__ SelState sel_advance(SelState s, const uint32_t* h, int pass) {
+  const int lane = threadIdx.x & 63;
+  const uint4 c4 = *reinterpret_cast<const uint4*>(h + 4 * lane);
+  const uint32_t c[4] = {c4.x, c4.y, c4.z, c4.w};
+  const uint32_t tot = (c[0] + c[1]) + (c[2] + c[3]);
+  uint32_t incl = tot;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  const uint32_t excl = incl - tot;
+  const bool mine = s.valid != 0u && excl <= s.k && s.k < incl;   // the lane whose bins hold rank k
+  uint32_t digit = 0u, below = excl;
+  if (mine) {
+    uint32_t d = 0u;
+#pragma unroll
+    for (uint32_t j = 0; j < 3; ++j) {
+      if (d == j && s.k >= below + c[j]) {
+        below += c[j];
+        d = j + 1u;
+      }
+    }
+    digit = 4u * uint32_t(lane) + d;
+  }
+  const unsigned long long b = __ballot(mine);
+  if (b != 0ull) {
+    const int src = __builtin_ctzll(b);
+    digit = uint32_t(__shfl(int(digit), src, 64));
+    below = uint32_t(__shfl(int(below), src, 64));
+    s.prefix |= digit << sel_shift(pass);
+    s.k -= below;
+  }
+  return s;
+}
+
+// State of segment sg before pass `pass` (0..3; 4 = the answer), by one full
+// wave.  Pass 0 reads the initial state.
+__device__ __forceinline__ SelState sel_state(const SelSet& S, int sg, int pass) {
+  if (pass == 0) return S.st[sg];
+  return sel_advance(S.st[size_t((pass - 1) & 1) * size_t(S.nseg) + size_t(sg)], sel_hist(S, pass - 1, sg),
+                     pass - 1);
+}
+
+// block 0 of a launch, one lane: keep the state for the next launch
+__device__ __forceinline__ void sel_store(const SelSet& S, int sg, int pass, const SelState& s) {
+  S.st[size_t(pass & 1) * size_t(S.nseg) + size_t(sg)] = s;
+}
 
 }  // namespace lv
