@@ -364,6 +364,36 @@ def main():
            "step_frac": round((b_fwd + b_bwd) / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     log(f"[bench] whole-path HBM fractions {hbm}")
 
+    # ---- pruning stability guards (the next row after the hot path): one
+    # adaptation step on this workload's w_max, the cap binding
+    gbins = torch.empty(vox.n, dtype=torch.uint8, device=dev)
+    lv.depth_quantile(ctx, vox, frame, wmax, n_bins, 0.1, q_ws, tau, prune, gbins, stream=stream)
+    gws = torch.empty(lv.guard_workspace_size(vox.n), dtype=torch.uint8, device=dev)
+    ema = torch.empty(vox.n, device=dev)
+    gstate = torch.empty(vox.n, dtype=torch.uint8, device=dev)
+    gprune = torch.empty(vox.n, dtype=torch.uint8, device=dev)
+    npr = torch.empty(1, dtype=torch.int32, device=dev)
+    gp = lv.guard_params(alpha=0.5, cap_frac=0.01)
+    gtimes = []
+    for rep in range(max(5, args.steps // 2) + 2):
+        with torch.cuda.stream(stream):
+            ema.fill_(0.5)      # every voxel starts halfway: many candidates, the cap binds
+            gstate.fill_(1)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        lv.prune_guard(ctx, vox, frame, wmax, gbins, tau, n_bins, gp, gws, ema, gstate, gprune, npr,
+                       stream=stream)
+        e1.record(stream)
+        e1.synchronize()
+        if rep >= 2:
+            gtimes.append(e0.elapsed_time(e1))
+    g_ms = float(np.median(gtimes))
+    g_bytes = 23 * scene.n   # w_max, bin, ema, state, level, ijk read; ema, state, prune written
+    guard = {"voxels": scene.n, "ms": round(g_ms, 4), "pruned": int(npr.cpu().numpy()[0]),
+             "alg_bytes": int(g_bytes),
+             "hbm_frac": round(g_bytes / (g_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    log(f"[bench] prune guard {guard}")
+
     # ---- the other workloads
     others = {}
     for name in [w for w in args.other_workloads.split(",") if w]:
@@ -428,6 +458,7 @@ def main():
         "phases_ms": {k: round(v, 4) for k, v in phases.items()},
         "whole_path_hbm": hbm,
         "other_workloads": others,
+        "next_rows": {"prune_guard": guard},
     }
     print(json.dumps(out), flush=True)
     ctx.close()

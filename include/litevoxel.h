@@ -215,6 +215,42 @@ lv_status lv_depth_quantile(lv_context* ctx, const lv_voxels* vox, const lv_fram
                             const float* wmax, int32_t n_bins, double q, void* workspace,
                             float* tau, uint8_t* prune, uint8_t* bins, hipStream_t stream);
 
+/* ------------------------------------------- pruning stability guards
+ * One adaptation step of the three guards on pruning (Sec. IV-C, guards
+ * i-iii), applied on top of lv_depth_quantile (same vox/frame; its tau and
+ * bins, with the same n_bins; bin values >= n_bins are read as n_bins - 1):
+ *   x_v = 1 if w_max_v > tau[bin_v], else 0      (inside score)
+ *   i.   ema_v <- (1 - alpha) ema_v + alpha x_v;  state_v <- 0 (out) if
+ *        ema_v < m_low, 1 (in) if ema_v > m_high, else unchanged
+ *   ii.  protected if delta_v is finite and h_v < rho delta_v (h_v = half
+ *        edge, delta_v the footprint defined for lv_depth_quantile), or
+ *        w_max_v >= w_keep                         (keep-halo)
+ *   iii. candidates = out and not protected; the first min(cap, count) of
+ *        them in the order (ema_v, v) get prune_v = 1, cap =
+ *        floor(cap_frac n) in double; ema ordered as binary32 (-0 < +0).
+ * All arithmetic binary32, one rounded operation at a time as written.
+ * ema [n] (f32) and state [n] (u8) are caller-owned device arrays updated in
+ * place (start new voxels at 1.0 and 1); prune [n] (u8) is written;
+ * n_pruned (device u32, nullable) receives the number pruned.  Argument
+ * errors (null pointers for n > 0, alpha outside (0, 1], m_low > m_high,
+ * rho < 0, cap_frac outside [0, 1], n_bins outside [1, 64]) return
+ * LV_ERR_ARG before anything is enqueued.  The paper fixes none of the
+ * constants; lv_default_guard gives alpha 0.3, m_low 0.3, m_high 0.7,
+ * rho 0.25, w_keep 0.5, cap_frac 0.05. */
+typedef struct {
+  float alpha;
+  float m_low, m_high;
+  float rho;
+  float w_keep;
+  double cap_frac;
+} lv_guard_params;
+void lv_default_guard(lv_guard_params* p);
+uint64_t lv_guard_workspace_size(int64_t n);
+lv_status lv_prune_guard(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
+                         const float* wmax, const uint8_t* bins, const float* tau, int32_t n_bins,
+                         const lv_guard_params* params, void* workspace, float* ema,
+                         uint8_t* state, uint8_t* prune, uint32_t* n_pruned, hipStream_t stream);
+
 /* ------------------------------------------------------ execution structure
  * Graph capture: between lv_graph_begin and lv_graph_end every call that
  * enqueues on `stream` is recorded instead of run; lv_graph_launch replays

@@ -39,6 +39,11 @@ class LvSettings(ctypes.Structure):
                 ("pair_capacity", c_uint64)]
 
 
+class LvGuardParams(ctypes.Structure):
+    _fields_ = [("alpha", c_float), ("m_low", c_float), ("m_high", c_float), ("rho", c_float),
+                ("w_keep", c_float), ("cap_frac", c_double)]
+
+
 # name -> (restype, argtypes)
 P = c_void_p
 _SIGS = {
@@ -65,6 +70,10 @@ _SIGS = {
     "lv_quantile_workspace_size": (c_uint64, [c_int64, c_int32]),
     "lv_depth_quantile": (c_int32, [P, POINTER(LvVoxels), POINTER(LvFrame), P, c_int32, c_double,
                                     P, P, P, P, P]),
+    "lv_default_guard": (None, [POINTER(LvGuardParams)]),
+    "lv_guard_workspace_size": (c_uint64, [c_int64]),
+    "lv_prune_guard": (c_int32, [P, POINTER(LvVoxels), POINTER(LvFrame), P, P, P, c_int32,
+                                 POINTER(LvGuardParams), P, P, P, P, P, P]),
     "lv_graph_begin": (c_int32, [P, P]),
     "lv_graph_end": (c_int32, [P, P]),
     "lv_graph_launch": (c_int32, [P, P]),

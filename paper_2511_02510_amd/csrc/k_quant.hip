@@ -85,22 +85,7 @@ __global__ void k_q_setup(QuantWS w, int B, uint32_t n) {
 __global__ __launch_bounds__(256) void k_q_delta(RasterArgs a, QuantWS w) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
-  const int64_t n = a.n;
-  const int l = a.level[i];
-  const float e = ldexpf(a.root_size, -l);
-  const float h = 0.5f * e;
-  const float x0 = (a.root_min[0] + float(a.ijk[i]) * e) + h;
-  const float x1 = (a.root_min[1] + float(a.ijk[n + i]) * e) + h;
-  const float x2 = (a.root_min[2] + float(a.ijk[2 * n + i]) * e) + h;
-  float delta = INFINITY;
-  for (int v = 0; v < a.V; ++v) {
-    const lv_camera& c = a.cams[v];
-    const float q0 = x0 - c.o[0], q1 = x1 - c.o[1], q2 = x2 - c.o[2];
-    float z = c.R[6] * q0 + c.R[7] * q1;
-    z = z + c.R[8] * q2;
-    if (z > 0.0f) delta = fminf(delta, z / c.fx);
-  }
-  w.dkey[i] = f2key(delta);
+  w.dkey[i] = f2key(voxel_footprint(a, i));
   w.wkey[i] = f2key(a.wmax[i]);
 }
 

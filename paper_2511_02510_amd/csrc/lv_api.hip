@@ -22,6 +22,10 @@ hipError_t run_l1_grad(const lv_camera* cams_dev, int V, uint64_t max_pix, const
                        hipStream_t s);
 hipError_t run_depth_quantile(const RasterArgs& a, int B, double q, void* ws, float* tau,
                               uint8_t* prune, uint8_t* out_bins, hipStream_t s);
+uint64_t guard_ws_bytes(int64_t n);
+hipError_t run_prune_guard(const RasterArgs& a, const uint8_t* bins, const float* tau, int nb,
+                           const GuardParams& p, void* ws, float* ema, uint8_t* state,
+                           uint8_t* prune, uint32_t* n_pruned, hipStream_t s);
 }  // namespace lv
 
 struct lv_context {
@@ -451,6 +455,54 @@ lv_status lv_depth_quantile(lv_context* ctx, const lv_voxels* vox, const lv_fram
   lv::RasterArgs a = make_args(L, workspace, vox, frame, nullptr);
   a.wmax = const_cast<float*>(wmax);
   LV_TRY(lv::run_depth_quantile(a, n_bins, q, workspace, tau, prune, bins, stream), "depth_quantile");
+  return LV_OK;
+}
+
+void lv_default_guard(lv_guard_params* p) {
+  if (!p) return;
+  p->alpha = 0.3f;
+  p->m_low = 0.3f;
+  p->m_high = 0.7f;
+  p->rho = 0.25f;
+  p->w_keep = 0.5f;
+  p->cap_frac = 0.05;
+}
+
+uint64_t lv_guard_workspace_size(int64_t n) {
+  if (n < 0) return 0;
+  return lv::guard_ws_bytes(n);
+}
+
+lv_status lv_prune_guard(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
+                         const float* wmax, const uint8_t* bins, const float* tau, int32_t n_bins,
+                         const lv_guard_params* params, void* workspace, float* ema,
+                         uint8_t* state, uint8_t* prune, uint32_t* n_pruned, hipStream_t stream) {
+  if (!ctx) return LV_ERR_ARG;
+  lv_status s = check_voxels(ctx, vox, false);
+  if (s != LV_OK) return s;
+  if ((s = check_frame(ctx, frame)) != LV_OK) return s;
+  if (!params) return fail(ctx, LV_ERR_ARG, "params must be non-NULL");
+  const lv_guard_params& g = *params;
+  if (n_bins < 1 || n_bins > 64) return fail(ctx, LV_ERR_ARG, "n_bins must be in [1, 64]");
+  if (!(g.alpha > 0.0f && g.alpha <= 1.0f)) return fail(ctx, LV_ERR_ARG, "alpha must be in (0, 1]");
+  if (!(g.m_low <= g.m_high)) return fail(ctx, LV_ERR_ARG, "m_low must not exceed m_high");
+  if (!(g.rho >= 0.0f)) return fail(ctx, LV_ERR_ARG, "rho must be >= 0");
+  if (!(g.cap_frac >= 0.0 && g.cap_frac <= 1.0)) return fail(ctx, LV_ERR_ARG, "cap_frac must be in [0, 1]");
+  if (!workspace || (vox->n > 0 && (!wmax || !bins || !tau || !ema || !state || !prune)))
+    return fail(ctx, LV_ERR_ARG, "workspace/wmax/bins/tau/ema/state/prune must be non-NULL");
+  if (vox->n > int64_t(0x7FFFFFFF)) return fail(ctx, LV_ERR_ARG, "n must be below 2^31");
+  lv::Layout L;
+  lv::RasterArgs a = make_args(L, workspace, vox, frame, nullptr);
+  a.wmax = const_cast<float*>(wmax);
+  lv::GuardParams p;
+  p.alpha = g.alpha;
+  p.m_low = g.m_low;
+  p.m_high = g.m_high;
+  p.rho = g.rho;
+  p.w_keep = g.w_keep;
+  p.cap = uint32_t(std::floor(g.cap_frac * double(vox->n)));
+  LV_TRY(lv::run_prune_guard(a, bins, tau, n_bins, p, workspace, ema, state, prune, n_pruned, stream),
+         "prune_guard");
   return LV_OK;
 }
 

@@ -176,6 +176,12 @@ inline WS bind(const Layout& L, void* base) {
   return w;
 }
 
+// constants of the pruning guards (cap = floor(cap_frac n), taken on the host)
+struct GuardParams {
+  float alpha, m_low, m_high, rho, w_keep;
+  uint32_t cap;
+};
+
 // Everything the rasterizer kernels read, passed by value.
 struct RasterArgs {
   WS ws;
@@ -211,6 +217,29 @@ struct RasterArgs {
 };
 
 // ---------------------------------------------------------------- helpers
+// Inter-ray spacing at voxel i's centre (the footprint of eq. 13-14): the
+// minimum over views with z_c > 0 of z_c / fx, +inf if no view has the
+// centre in front.  Binary32, one rounded operation at a time in the order
+// written, so that the decisions taken on it are exact.
+__device__ __forceinline__ float voxel_footprint(const RasterArgs& a, int64_t i) {
+  const int64_t n = a.n;
+  const int l = a.level[i];
+  const float e = ldexpf(a.root_size, -l);
+  const float h = 0.5f * e;
+  const float x0 = (a.root_min[0] + float(a.ijk[i]) * e) + h;
+  const float x1 = (a.root_min[1] + float(a.ijk[n + i]) * e) + h;
+  const float x2 = (a.root_min[2] + float(a.ijk[2 * n + i]) * e) + h;
+  float delta = INFINITY;
+  for (int v = 0; v < a.V; ++v) {
+    const lv_camera& c = a.cams[v];
+    const float q0 = x0 - c.o[0], q1 = x1 - c.o[1], q2 = x2 - c.o[2];
+    float z = c.R[6] * q0 + c.R[7] * q1;
+    z = z + c.R[8] * q2;
+    if (z > 0.0f) delta = fminf(delta, z / c.fx);
+  }
+  return delta;
+}
+
 // first pair of tile t (tile t + 1's start is its end), clipped to capacity
 __device__ __forceinline__ uint64_t tile_begin(const RasterArgs& a, uint32_t t) {
   const uint64_t s = a.ws.tstart[uint64_t(t) * kSpread];

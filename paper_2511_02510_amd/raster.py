@@ -240,6 +240,32 @@ def depth_quantile(ctx, vox, frame, wmax, n_bins, q, workspace, tau, prune, bins
                                         _p(prune), _p(bins), _stream(stream)), "lv_depth_quantile")
 
 
+def guard_params(**kw):
+    """lv_guard_params with the library defaults, overridden by keyword
+    (alpha, m_low, m_high, rho, w_keep, cap_frac)."""
+    p = _abi.LvGuardParams()
+    _abi.lib().lv_default_guard(ctypes.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise TypeError(f"unknown guard parameter {k}")
+        setattr(p, k, v)
+    return p
+
+
+def guard_workspace_size(n: int) -> int:
+    return int(_abi.lib().lv_guard_workspace_size(int(n)))
+
+
+def prune_guard(ctx, vox, frame, wmax, bins, tau, n_bins, params, workspace, ema, state, prune,
+                n_pruned=None, stream=None):
+    """One adaptation step of the pruning guards (lv_prune_guard): updates
+    ema and state in place and writes prune."""
+    ctx.check(ctx.lib.lv_prune_guard(ctx.h, ctypes.byref(vox.struct), ctypes.byref(frame.struct),
+                                     _p(wmax), _p(bins), _p(tau), int(n_bins), ctypes.byref(params),
+                                     _p(workspace), _p(ema), _p(state), _p(prune), _p(n_pruned),
+                                     _stream(stream)), "lv_prune_guard")
+
+
 def graph_begin(ctx, stream):
     ctx.check(ctx.lib.lv_graph_begin(ctx.h, _stream(stream)), "lv_graph_begin")
 
