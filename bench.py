@@ -394,6 +394,39 @@ def main():
              "hbm_frac": round(g_bytes / (g_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     log(f"[bench] prune guard {guard}")
 
+    # ---- priority-driven subdivision (the next row after the guards): the
+    # footprint percentiles, the selection with w_max as usefulness, the split
+    def gpu_ms(fn, reps):
+        ts = []
+        for rep in range(reps + 2):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            e1.synchronize()
+            if rep >= 2:
+                ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+
+    sws = torch.empty(lv.split_workspace_size(vox.n), dtype=torch.uint8, device=dev)
+    zr = torch.empty(2, device=dev)
+    ssplit = torch.empty(vox.n, dtype=torch.uint8, device=dev)
+    nsp = torch.empty(1, dtype=torch.int32, device=dev)
+    spp = lv.split_params()
+    reps = max(5, args.steps // 2)
+    t_range = gpu_ms(lambda: lv.footprint_range(ctx, vox, frame, sws, zr, stream=stream), reps)
+    t_sel = gpu_ms(lambda: lv.subdivide_select(ctx, vox, frame, wmax, zr, spp, sws, ssplit, None, nsp,
+                                               stream=stream), reps)
+    n_split = int(nsp.cpu().numpy()[0])
+    n_out = scene.n + 7 * n_split
+    t_apply = gpu_ms(lambda: lv.subdivide_apply(ctx, vox, ssplit, n_out, sws, stream=stream), reps)
+    per_voxel = 7 + 32 + 4 * int(vox.sh.shape[0])      # ijk + level, densities, SH
+    subdiv = {"voxels": scene.n, "splits": n_split, "voxels_after": n_out,
+           "range_ms": round(t_range, 4), "select_ms": round(t_sel, 4), "apply_ms": round(t_apply, 4),
+           "apply_alg_bytes": int(per_voxel * (scene.n + n_out)),
+           "apply_hbm_frac": round(per_voxel * (scene.n + n_out) / (t_apply * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    log(f"[bench] subdivision {subdiv}")
+
     # ---- the other workloads
     others = {}
     for name in [w for w in args.other_workloads.split(",") if w]:
@@ -458,7 +491,7 @@ def main():
         "phases_ms": {k: round(v, 4) for k, v in phases.items()},
         "whole_path_hbm": hbm,
         "other_workloads": others,
-        "next_rows": {"prune_guard": guard},
+        "next_rows": {"prune_guard": guard, "subdivide": subdiv},
     }
     print(json.dumps(out), flush=True)
     ctx.close()

@@ -251,6 +251,56 @@ lv_status lv_prune_guard(lv_context* ctx, const lv_voxels* vox, const lv_frame* 
                          const lv_guard_params* params, void* workspace, float* ema,
                          uint8_t* state, uint8_t* prune, uint32_t* n_pruned, hipStream_t stream);
 
+/* ------------------------------------- priority-driven subdivision (Sec. IV-D)
+ * Three calls, one workspace (>= lv_split_workspace_size(n)):
+ *  lv_footprint_range: range [2] (device f32) = nearest-rank 5th and 95th
+ *    percentiles over all voxels of delta (the footprint defined for
+ *    lv_depth_quantile); 0, 0 without voxels.  One way to keep the running
+ *    percentiles of eq. 14.
+ *  lv_subdivide_select (eq. 13-16): with h_v the half edge and
+ *    z~_v = clip((delta_v - range[0]) / (range[1] - range[0]), 0, 1)
+ *    (+inf -> 1; range[1] <= range[0] or +inf -> 0 for finite delta),
+ *      eligible_v = l_v < LV_MAX_LEVEL and delta_v finite and h_v > kappa delta_v
+ *      priority_v = score_v (1 + beta z~_v)
+ *    split [n] (u8) marks the first min(max_splits, count) eligible voxels
+ *    with priority > 0 in the order (priority descending, index ascending).
+ *    score [n] (f32) is the caller's running usefulness score P_v (the paper
+ *    leaves it open).  priority [n] (f32, nullable) and n_split (device u32,
+ *    nullable) are optional outputs.
+ *  lv_subdivide_apply: writes the refined set of n_out = n + 7 (#split)
+ *    leaves into caller-owned arrays laid out like lv_voxels with n_out
+ *    rows (ijk [3][n_out] u16, level [n_out] u8, density [8][n_out] f32,
+ *    sh [3 (deg+1)^2][n_out] f32): input order kept, each split voxel
+ *    replaced in place by its 8 children (child c = x + 2y + 4z bits,
+ *    ijk = 2 ijk + bits, level + 1), whose corner densities are the parent's
+ *    trilinear field at their corners (midpoints 0.5 a + 0.5 b along x,
+ *    then y, then z: the density field is unchanged) and whose SH are the
+ *    parent's.  Flags on leaves at LV_MAX_LEVEL are ignored.  n_needed
+ *    (device u64, nullable) receives n + 7 (#split); rows at or beyond n_out
+ *    are not written, so a wrong n_out gives a truncated set, never a write
+ *    out of bounds.  The output arrays must not alias the input.
+ * Binary32, one rounded operation at a time as written.  Argument errors
+ * (null pointers for n > 0, kappa or beta negative or not finite, n_out < n)
+ * return LV_ERR_ARG before anything is enqueued.  The paper fixes kappa ~ 1
+ * and beta in [0.1, 0.3]; lv_default_split gives kappa 1, beta 0.2,
+ * max_splits 8192. */
+typedef struct {
+  float kappa;
+  float beta;
+  uint32_t max_splits;
+} lv_split_params;
+void lv_default_split(lv_split_params* p);
+uint64_t lv_split_workspace_size(int64_t n);
+lv_status lv_footprint_range(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
+                             void* workspace, float* range, hipStream_t stream);
+lv_status lv_subdivide_select(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
+                              const float* score, const float* range, const lv_split_params* params,
+                              void* workspace, uint8_t* split, float* priority, uint32_t* n_split,
+                              hipStream_t stream);
+lv_status lv_subdivide_apply(lv_context* ctx, const lv_voxels* vox, const uint8_t* split,
+                             int64_t n_out, void* workspace, uint16_t* ijk, uint8_t* level,
+                             float* density, float* sh, uint64_t* n_needed, hipStream_t stream);
+
 /* ------------------------------------------------------ execution structure
  * Graph capture: between lv_graph_begin and lv_graph_end every call that
  * enqueues on `stream` is recorded instead of run; lv_graph_launch replays

@@ -18,7 +18,8 @@ voxel and the child initialisation open):
              mid(a, b) = 0.5 a + 0.5 b taken along x, then y, then z (exact
              refinement: the density field is unchanged); SH coefficients
              are copied.  The refined set keeps the input order, each split
-             voxel replaced in place by its 8 children.
+             voxel replaced in place by its 8 children; a split flag on a
+             leaf at the finest level is ignored.
 Binary32, one rounded operation at a time in the order written, wherever the
 result decides an integer or is stored.
 """
@@ -101,7 +102,7 @@ def child_densities(dens):
 def apply_split(scene, split):
     """The refined voxel set (same Scene type), input order kept."""
     from synth.scenes import Scene
-    split = np.asarray(split, dtype=bool)
+    split = np.asarray(split, dtype=bool) & (scene.level.astype(np.int32) < L_MAX)   # finest: no children
     n = scene.n
     reps = np.where(split, 8, 1)
     m = int(reps.sum())

@@ -44,6 +44,10 @@ class LvGuardParams(ctypes.Structure):
                 ("w_keep", c_float), ("cap_frac", c_double)]
 
 
+class LvSplitParams(ctypes.Structure):
+    _fields_ = [("kappa", c_float), ("beta", c_float), ("max_splits", ctypes.c_uint32)]
+
+
 # name -> (restype, argtypes)
 P = c_void_p
 _SIGS = {
@@ -74,6 +78,12 @@ _SIGS = {
     "lv_guard_workspace_size": (c_uint64, [c_int64]),
     "lv_prune_guard": (c_int32, [P, POINTER(LvVoxels), POINTER(LvFrame), P, P, P, c_int32,
                                  POINTER(LvGuardParams), P, P, P, P, P, P]),
+    "lv_default_split": (None, [POINTER(LvSplitParams)]),
+    "lv_split_workspace_size": (c_uint64, [c_int64]),
+    "lv_footprint_range": (c_int32, [P, POINTER(LvVoxels), POINTER(LvFrame), P, P, P]),
+    "lv_subdivide_select": (c_int32, [P, POINTER(LvVoxels), POINTER(LvFrame), P, P,
+                                      POINTER(LvSplitParams), P, P, P, P, P]),
+    "lv_subdivide_apply": (c_int32, [P, POINTER(LvVoxels), P, c_int64, P, P, P, P, P, P, P]),
     "lv_graph_begin": (c_int32, [P, P]),
     "lv_graph_end": (c_int32, [P, P]),
     "lv_graph_launch": (c_int32, [P, P]),

@@ -86,7 +86,7 @@ __global__ __launch_bounds__(256) void k_q_delta(RasterArgs a, QuantWS w) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
   w.dkey[i] = f2key(voxel_footprint(a, i));
-  w.wkey[i] = f2key(a.wmax[i]);
+  if (a.wmax) w.wkey[i] = f2key(a.wmax[i]);
 }
 
 // Histogram of the current digit for the selections of S.  dual: every
@@ -249,6 +249,35 @@ hipError_t run_depth_quantile(const RasterArgs& a, int B, double q, void* ws, fl
                          pass == 0 ? (const uint32_t*)w.cnt : (const uint32_t*)nullptr, q);
   }
   hipLaunchKernelGGL(k_q_prune, dim3(grid_for(a.n)), dim3(256), 0, s, a.n, B, w, a.wmax, tau, prune);
+  return hipGetLastError();
+}
+
+// p5 and p95 of the footprint alone (the running-percentile input of the
+// subdivision priority, eq. 14): 0 when there are no voxels
+__global__ void k_q_range(QuantWS w, float* range) {
+  if (threadIdx.x < 128) {
+    const int sg = int(threadIdx.x >> 6);
+    const SelState st = sel_state(w.pct, sg, 4);
+    if ((threadIdx.x & 63) == 0) range[sg] = st.valid ? key2f(st.prefix) : 0.0f;
+  }
+}
+
+uint64_t range_ws_bytes(int64_t n) { return quant_ws_bytes(n, 1); }
+
+hipError_t run_footprint_range(const RasterArgs& a, void* ws, float* range, hipStream_t s) {
+  QuantWS w = quant_bind(ws, a.n, 1);
+  RasterArgs b = a;
+  b.wmax = nullptr;
+  hipLaunchKernelGGL(k_q_setup, dim3(3), dim3(256), 0, s, w, 1, uint32_t(a.n));
+  if (a.n > 0) {
+    hipLaunchKernelGGL(k_q_delta, dim3(uint32_t((a.n + 255) / 256)), dim3(256), 0, s, b, w);
+    const uint32_t g = grid_for(a.n);
+    for (int pass = 0; pass < 4; ++pass)
+      hipLaunchKernelGGL(k_q_hist, dim3(g), dim3(256), hist_lds(2, kCopiesDual), s,
+                         (const uint32_t*)w.dkey, (const uint8_t*)nullptr, a.n, w.pct, pass, 1,
+                         kCopiesDual, (const uint32_t*)nullptr, 0.5);
+  }
+  hipLaunchKernelGGL(k_q_range, dim3(1), dim3(128), 0, s, w, range);
   return hipGetLastError();
 }
 

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "lv_common.h"
+#include "lv_select.h"
 
 namespace lv {
 uint64_t loss_ws_bytes(int V);
@@ -23,6 +24,14 @@ hipError_t run_l1_grad(const lv_camera* cams_dev, int V, uint64_t max_pix, const
 hipError_t run_depth_quantile(const RasterArgs& a, int B, double q, void* ws, float* tau,
                               uint8_t* prune, uint8_t* out_bins, hipStream_t s);
 uint64_t guard_ws_bytes(int64_t n);
+uint64_t split_ws_bytes(int64_t n);
+hipError_t run_footprint_range(const RasterArgs& a, void* ws, float* range, hipStream_t s);
+hipError_t run_split_select(const RasterArgs& a, const float* score, const float* range,
+                            const SplitParams& p, void* ws, uint8_t* split, float* priority,
+                            uint32_t* n_split, hipStream_t s);
+hipError_t run_split_apply(const RasterArgs& a, const uint8_t* split, int64_t m, void* ws,
+                           uint16_t* ijk, uint8_t* level, float* density, float* sh,
+                           uint64_t* needed, hipStream_t s);
 hipError_t run_prune_guard(const RasterArgs& a, const uint8_t* bins, const float* tau, int nb,
                            const GuardParams& p, void* ws, float* ema, uint8_t* state,
                            uint8_t* prune, uint32_t* n_pruned, hipStream_t s);
@@ -169,9 +178,11 @@ lv::RasterArgs make_args(const lv::Layout& L, void* ws, const lv_voxels* vx, con
   a.level = vx->level;
   a.density = vx->density;
   a.sh = vx->sh;
-  a.V = fr->n_views;
-  a.cams = fr->cams_dev;
-  for (int k = 0; k < 3; ++k) a.bg[k] = fr->bg[k];
+  if (fr) {   // calls that need no views pass none
+    a.V = fr->n_views;
+    a.cams = fr->cams_dev;
+    for (int k = 0; k < 3; ++k) a.bg[k] = fr->bg[k];
+  }
   a.TS = L.TS;
   a.T = L.T;
   a.P = L.P;
@@ -503,6 +514,74 @@ lv_status lv_prune_guard(lv_context* ctx, const lv_voxels* vox, const lv_frame* 
   p.cap = uint32_t(std::floor(g.cap_frac * double(vox->n)));
   LV_TRY(lv::run_prune_guard(a, bins, tau, n_bins, p, workspace, ema, state, prune, n_pruned, stream),
          "prune_guard");
+  return LV_OK;
+}
+
+void lv_default_split(lv_split_params* p) {
+  if (!p) return;
+  p->kappa = 1.0f;
+  p->beta = 0.2f;
+  p->max_splits = 8192u;
+}
+
+uint64_t lv_split_workspace_size(int64_t n) {
+  if (n < 0) return 0;
+  return lv::split_ws_bytes(n);
+}
+
+lv_status lv_footprint_range(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
+                             void* workspace, float* range, hipStream_t stream) {
+  if (!ctx) return LV_ERR_ARG;
+  lv_status s = check_voxels(ctx, vox, false);
+  if (s != LV_OK) return s;
+  if ((s = check_frame(ctx, frame)) != LV_OK) return s;
+  if (!workspace || !range) return fail(ctx, LV_ERR_ARG, "workspace/range must be non-NULL");
+  lv::Layout L;
+  lv::RasterArgs a = make_args(L, workspace, vox, frame, nullptr);
+  LV_TRY(lv::run_footprint_range(a, workspace, range, stream), "footprint_range");
+  return LV_OK;
+}
+
+lv_status lv_subdivide_select(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
+                              const float* score, const float* range, const lv_split_params* params,
+                              void* workspace, uint8_t* split, float* priority, uint32_t* n_split,
+                              hipStream_t stream) {
+  if (!ctx) return LV_ERR_ARG;
+  lv_status s = check_voxels(ctx, vox, false);
+  if (s != LV_OK) return s;
+  if ((s = check_frame(ctx, frame)) != LV_OK) return s;
+  if (!params) return fail(ctx, LV_ERR_ARG, "params must be non-NULL");
+  if (!(std::isfinite(params->kappa) && params->kappa >= 0.0f))
+    return fail(ctx, LV_ERR_ARG, "kappa must be finite and >= 0");
+  if (!(std::isfinite(params->beta) && params->beta >= 0.0f))
+    return fail(ctx, LV_ERR_ARG, "beta must be finite and >= 0");
+  if (!workspace || (vox->n > 0 && (!score || !range || !split)))
+    return fail(ctx, LV_ERR_ARG, "workspace/score/range/split must be non-NULL");
+  lv::Layout L;
+  lv::RasterArgs a = make_args(L, workspace, vox, frame, nullptr);
+  lv::SplitParams p;
+  p.kappa = params->kappa;
+  p.beta = params->beta;
+  p.max_splits = params->max_splits;
+  LV_TRY(lv::run_split_select(a, score, range, p, workspace, split, priority, n_split, stream),
+         "subdivide_select");
+  return LV_OK;
+}
+
+lv_status lv_subdivide_apply(lv_context* ctx, const lv_voxels* vox, const uint8_t* split,
+                             int64_t n_out, void* workspace, uint16_t* ijk, uint8_t* level,
+                             float* density, float* sh, uint64_t* n_needed, hipStream_t stream) {
+  if (!ctx) return LV_ERR_ARG;
+  lv_status s = check_voxels(ctx, vox, true);
+  if (s != LV_OK) return s;
+  if (n_out < vox->n || n_out > 8 * vox->n)
+    return fail(ctx, LV_ERR_ARG, "n_out must lie in [n, 8 n]");
+  if (!workspace || (vox->n > 0 && (!split || !ijk || !level || !density || !sh)))
+    return fail(ctx, LV_ERR_ARG, "workspace/split/ijk/level/density/sh must be non-NULL");
+  lv::Layout L;
+  lv::RasterArgs a = make_args(L, workspace, vox, nullptr, nullptr);
+  LV_TRY(lv::run_split_apply(a, split, n_out, workspace, ijk, level, density, sh, n_needed, stream),
+         "subdivide_apply");
   return LV_OK;
 }
 

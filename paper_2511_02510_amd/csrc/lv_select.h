@@ -108,4 +108,53 @@ __device__ __forceinline__ void sel_store(const SelSet& S, int sg, int pass, con
   S.st[size_t(pass & 1) * size_t(S.nseg) + size_t(sg)] = s;
 }
 
+// ------------------------------------------------------- capped selection
+// Of the candidates among n items, marks the first min(cap, #candidates) in
+// the order (key, index): an exact radix select of the cap-th smallest key
+// among the candidates, then the candidates equal to it taken in index order
+// (block-ordered count).  A producer kernel with at most kCapFillBlocks
+// blocks writes key[i] and cand[i] for every item and its block's candidate
+// count with cap_store_block_count; launch_cap_setup must run before it.
+constexpr int kCapFillBlocks = 1024;
+
+// constants of the subdivision selection (eq. 13-16)
+struct SplitParams {
+  float kappa, beta;
+  uint32_t max_splits;
+};
+
+constexpr int kCapHistBlocks = 256;
+constexpr int kCapPer = 2048;   // items per block of the block-ordered passes
+
+struct CapWS {
+  uint32_t* key;     // [n]
+  uint8_t* cand;     // [n]
+  uint32_t* ublk;    // [kCapFillBlocks] candidates per producer block
+  uint32_t* eqblk;   // [ceil(n / kCapPer)] candidates equal to the cutoff per block
+  uint32_t* cnt;     // [0]: candidates
+  SelSet sel;        // one selection: hist [4][256], st [2]
+};
+
+uint64_t cap_ws_bytes(int64_t n);
+CapWS cap_bind(void* base, int64_t n);
+hipError_t launch_cap_setup(const CapWS& w, uint32_t* count_out, hipStream_t s);
+// mask[i] = 1 for the marked items, else 0; count_out (nullable) = how many
+hipError_t launch_cap_select(const CapWS& w, int64_t n, uint32_t cap, uint8_t* mask,
+                             uint32_t* count_out, hipStream_t s);
+
+// block-wide sum of the calling threads' candidate counts into ublk
+// (every thread of the block must call it)
+__device__ __forceinline__ void cap_store_block_count(const CapWS& w, uint32_t mine) {
+  __shared__ uint32_t s_c[32];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) mine += uint32_t(__shfl_xor(int(mine), o, 64));
+  if ((threadIdx.x & 63) == 0) s_c[threadIdx.x >> 6] = mine;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+    for (uint32_t k = 0; k < (blockDim.x + 63) / 64; ++k) t += s_c[k];
+    w.ublk[blockIdx.x] = t;
+  }
+}
+
 }  // namespace lv

@@ -266,6 +266,53 @@ def prune_guard(ctx, vox, frame, wmax, bins, tau, n_bins, params, workspace, ema
                                      _stream(stream)), "lv_prune_guard")
 
 
+def split_params(**kw):
+    """lv_split_params with the library defaults (kappa 1, beta 0.2,
+    max_splits 8192), overridden by keyword."""
+    p = _abi.LvSplitParams()
+    _abi.lib().lv_default_split(ctypes.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise TypeError(f"unknown split parameter {k}")
+        setattr(p, k, v)
+    return p
+
+
+def split_workspace_size(n: int) -> int:
+    return int(_abi.lib().lv_split_workspace_size(int(n)))
+
+
+def footprint_range(ctx, vox, frame, workspace, range_out, stream=None):
+    """range_out [2] (device f32) = 5th and 95th percentiles of the footprint."""
+    ctx.check(ctx.lib.lv_footprint_range(ctx.h, ctypes.byref(vox.struct), ctypes.byref(frame.struct),
+                                         _p(workspace), _p(range_out), _stream(stream)),
+              "lv_footprint_range")
+
+
+def subdivide_select(ctx, vox, frame, score, range_in, params, workspace, split, priority=None,
+                     n_split=None, stream=None):
+    ctx.check(ctx.lib.lv_subdivide_select(ctx.h, ctypes.byref(vox.struct), ctypes.byref(frame.struct),
+                                          _p(score), _p(range_in), ctypes.byref(params),
+                                          _p(workspace), _p(split), _p(priority), _p(n_split),
+                                          _stream(stream)), "lv_subdivide_select")
+
+
+def subdivide_apply(ctx, vox, split, n_out, workspace, n_needed=None, stream=None) -> "Voxels":
+    """The refined voxel set with n_out = n + 7 (#split) leaves (new device
+    arrays; vox is left as it is)."""
+    dev = vox.level.device
+    n_out = int(n_out)
+    K = 3 * (vox.sh_degree + 1) ** 2
+    ijk = torch.empty((3, n_out), dtype=torch.int16, device=dev)
+    level = torch.empty(n_out, dtype=torch.uint8, device=dev)
+    dens = torch.empty((8, n_out), dtype=torch.float32, device=dev)
+    sh = torch.empty((K, n_out), dtype=torch.float32, device=dev)
+    ctx.check(ctx.lib.lv_subdivide_apply(ctx.h, ctypes.byref(vox.struct), _p(split), n_out,
+                                         _p(workspace), _p(ijk), _p(level), _p(dens), _p(sh),
+                                         _p(n_needed), _stream(stream)), "lv_subdivide_apply")
+    return Voxels(ijk, level, dens, sh, vox.root_min, vox.root_size, vox.sh_degree)
+
+
 def graph_begin(ctx, stream):
     ctx.check(ctx.lib.lv_graph_begin(ctx.h, _stream(stream)), "lv_graph_begin")
 
