@@ -106,6 +106,42 @@ def step_bytes(N, M, Q, P, K):
     return b_fwd, b_bwd
 
 
+def training_step(lv, ctx, r, vox, frame, target, gamma, form, bufs, stream, side, quantile,
+                  verify=False, overlap=True):
+    """One step: forward, loss weight, L1 gradient, backward (+ depth quantile).
+    With overlap the loss weight (it needs only the target and gamma) runs on
+    `side` beside the forward, and the depth quantile (it needs only w_max)
+    beside the backward; events join the two streams, also inside a captured
+    graph.  Without overlap everything runs in order on `stream`."""
+    import torch
+    rgb, depth, alpha, wmax, weight, lw_ws, loss, d_rgb, dd, dsh, nb, q_ws, tau, prune = bufs
+    aux = side if overlap else stream
+    if overlap:
+        e0 = torch.cuda.Event()
+        e0.record(stream)
+        side.wait_event(e0)
+    lv.lf_weight(ctx, frame, target, gamma, form, 1e-3, weight, lw_ws, stream=aux)
+    if overlap:
+        e_w = torch.cuda.Event()
+        e_w.record(side)
+    r.forward(rgb, depth, alpha, wmax, stream=stream, verify=verify)
+    if overlap:
+        e_f = torch.cuda.Event()
+        e_f.record(stream)
+        stream.wait_event(e_w)
+    lv.l1_grad(ctx, frame, rgb, target, weight, loss, d_rgb, stream=stream)
+    if quantile and overlap:
+        side.wait_event(e_f)
+        lv.depth_quantile(ctx, vox, frame, wmax, nb, 0.1, q_ws, tau, prune, stream=side)
+        e_q = torch.cuda.Event()
+        e_q.record(side)
+    r.backward(d_rgb, None, None, dd, dsh, stream=stream)
+    if quantile and not overlap:
+        lv.depth_quantile(ctx, vox, frame, wmax, nb, 0.1, q_ws, tau, prune, stream=stream)
+    if quantile and overlap:
+        stream.wait_event(e_q)
+
+
 def measure_workload(lv, ctx, name, tile, chunk, reps, warmup, quantile, form, gamma):
     """Forward and whole-step MP/s of another named workload (graph replay)."""
     import torch
@@ -131,17 +167,15 @@ def measure_workload(lv, ctx, name, tile, chunk, reps, warmup, quantile, form, g
     tau = torch.empty(nb, device=dev)
     prune = torch.empty(vox.n, dtype=torch.uint8, device=dev)
     stream = torch.cuda.Stream()
+    side = torch.cuda.Stream()
+    bufs = (rgb, depth, alpha, wmax, weight, lw_ws, loss, d_rgb, dd, dsh, nb, q_ws, tau, prune)
 
     def fwd(verify=False):
         r.forward(rgb, depth, alpha, wmax, stream=stream, verify=verify)
 
     def step(verify=False):
-        fwd(verify)
-        lv.lf_weight(ctx, frame, target, gamma, form, 1e-3, weight, lw_ws, stream=stream)
-        lv.l1_grad(ctx, frame, rgb, target, weight, loss, d_rgb, stream=stream)
-        r.backward(d_rgb, None, None, dd, dsh, stream=stream)
-        if quantile:
-            lv.depth_quantile(ctx, vox, frame, wmax, nb, 0.1, q_ws, tau, prune, stream=stream)
+        training_step(lv, ctx, r, vox, frame, target, gamma, form, bufs, stream, side, quantile,
+                      verify=verify)
 
     def timed(fn):
         with torch.cuda.stream(stream):
@@ -249,16 +283,17 @@ def main():
     gamma = lv.gamma_schedule(0.5, 1.0)
 
     stream = torch.cuda.Stream()
+    side = torch.cuda.Stream()   # both at the default priority
+    bufs = (rgb, depth, alpha, wmax, weight, lw_ws, loss, d_rgb, d_density, d_sh, n_bins, q_ws, tau,
+            prune)
 
-    def step(verify=False):
-        r.forward(rgb, depth, alpha, wmax, stream=stream, verify=verify)
-        lv.lf_weight(ctx, frame, target, gamma, 0, 1e-3, weight, lw_ws, stream=stream)
-        lv.l1_grad(ctx, frame, rgb, target, weight, loss, d_rgb, stream=stream)
-        r.backward(d_rgb, None, None, d_density, d_sh, stream=stream)
-        lv.depth_quantile(ctx, vox, frame, wmax, n_bins, q, q_ws, tau, prune, stream=stream)
+    def step(verify=False, overlap=True):
+        # q is 0.1 in both forms of the step
+        training_step(lv, ctx, r, vox, frame, target, gamma, 0, bufs, stream, side, True,
+                      verify=verify, overlap=overlap)
 
     with torch.cuda.stream(stream):
-        step(verify=True)           # sizes the pair buffers exactly
+        step(verify=True, overlap=False)    # sizes the pair buffers exactly
     torch.cuda.synchronize()
     fits, Q = lv.check_overflow(ctx, vox, frame, r.st, r.workspace, stream=stream)
     assert fits
@@ -266,7 +301,7 @@ def main():
 
     if args.profile_steps > 0:
         for _ in range(args.profile_steps):
-            step()
+            step(overlap=False)     # one stream: kernel durations without neighbours
         torch.cuda.synchronize()
         log("[bench] profile steps done")
         return
@@ -275,15 +310,16 @@ def main():
     lv.set_timing(ctx, True)
     lv.read_timings(ctx)
     for _ in range(max(3, args.steps // 2)):
-        step()
+        step(overlap=False)
     ph = lv.read_timings(ctx)
     lv.set_timing(ctx, False)
     phases = {k: (ms / max(c, 1)) for k, (ms, c) in ph.items()}
     log("[bench] phase ms/launch: " + ", ".join(f"{k} {v:.3f}" for k, v in phases.items()))
 
-    # ---- graph capture of one whole step
+    # ---- graph capture of one whole step (loss weight and depth quantile on
+    # a second stream beside the forward and the backward)
     lv.graph_begin(ctx, stream)
-    step()
+    step(overlap=True)
     lv.graph_end(ctx, stream)
     for _ in range(args.warmup):
         lv.graph_launch(ctx, stream)
@@ -480,7 +516,9 @@ def main():
         "config": {"workload": f"{args.workload}: {scene.n} voxels (octree levels 7-11, shell + 10% "
                                f"clutter), SH degree 3, {len(cams)} ring views "
                                f"{[(c.width, c.height) for c in cams]}, {P} px per step",
-                   "tile": int(st.tile), "chunk": int(st.chunk), "pairs": int(Q)},
+                   "tile": int(st.tile), "chunk": int(st.chunk), "pairs": int(Q),
+                   "streams": "render and gradient on one stream; loss weight beside the forward "
+                              "and depth quantile beside the backward on a second (one graph)"},
         "roofline": roof,
         "cpu_baseline": cpu,
         "fwd_mp_s": round(P / fwd_ms / 1e3, 2),

@@ -265,6 +265,90 @@ def test_graph_replays_match_eager(ctx):
     assert np.abs(got[0].cpu().numpy() - ref["rgb"]).max() <= IMG_TOL
 
 
+def test_two_stream_graph_matches_eager(ctx):
+    """The loss weight on a second stream beside the forward and the depth
+    quantile beside the backward, joined by events and captured in one graph:
+    every replay (with eager work between them) equals the one-stream eager
+    step."""
+    import paper_2511_02510_amd as lv
+    import torch
+    scene = small_shell(20000, seed=29, lmin=5, lmax=9, clutter=0.1)
+    cams = [look_at((2.1, 0.5, 1.0), 80, 60), look_at((-0.6, 1.2, 2.1), 96, 40)]
+    rng = np.random.default_rng(30)
+    targets = [synth.make_target(rng, c.width, c.height) for c in cams]
+    dev = ctx.device
+    vox = lv.Voxels.from_scene(scene, dev)
+    frame = lv.Frame(cams, dev)
+    r = lv.Renderer(ctx, vox, frame, lv.settings(tile=16, chunk=64))
+    tgt = to_dev(np.concatenate([t.ravel() for t in targets]), dev)
+    rgb, depth, alpha = r.new_outputs()
+    wmax = torch.zeros(vox.n, device=dev)
+    weight = torch.empty(frame.P, device=dev)
+    lws = torch.empty(lv.lf_weight_workspace_size(2), dtype=torch.uint8, device=dev)
+    loss = torch.empty(2, device=dev)
+    d_rgb = torch.empty(3 * frame.P, device=dev)
+    dd = torch.empty_like(vox.density)
+    dsh = torch.empty_like(vox.sh)
+    qws = torch.empty(lv.quantile_workspace_size(vox.n, 16), dtype=torch.uint8, device=dev)
+    tau = torch.empty(16, device=dev)
+    prune = torch.empty(vox.n, dtype=torch.uint8, device=dev)
+    stream, side = torch.cuda.Stream(), torch.cuda.Stream()
+
+    def step(overlap):
+        wmax.zero_()
+        aux = side if overlap else stream
+        if overlap:
+            e0 = torch.cuda.Event()
+            e0.record(stream)
+            side.wait_event(e0)
+        lv.lf_weight(ctx, frame, tgt, 0.5, 1, 1e-3, weight, lws, stream=aux)
+        if overlap:
+            e_w = torch.cuda.Event()
+            e_w.record(side)
+        r.forward(rgb, depth, alpha, wmax, stream=stream, verify=False)
+        if overlap:
+            e_f = torch.cuda.Event()
+            e_f.record(stream)
+            stream.wait_event(e_w)
+        lv.l1_grad(ctx, frame, rgb, tgt, weight, loss, d_rgb, stream=stream)
+        if overlap:
+            side.wait_event(e_f)
+        lv.depth_quantile(ctx, vox, frame, wmax, 16, 0.1, qws, tau, prune, stream=aux)
+        if overlap:
+            e_q = torch.cuda.Event()
+            e_q.record(side)
+        r.backward(d_rgb, None, None, dd, dsh, stream=stream)
+        if overlap:
+            stream.wait_event(e_q)
+
+    def snap():
+        torch.cuda.synchronize()
+        return [x.clone() for x in (rgb, depth, alpha, wmax, loss, weight, tau, prune, dd, dsh)]
+
+    say("two-stream graph capture and replays")
+    with torch.cuda.stream(stream):
+        r.forward(rgb, depth, alpha, wmax, stream=stream, verify=True)   # size capacity (syncs)
+        step(False)
+    eager = snap()
+    with torch.cuda.stream(stream):
+        lv.graph_begin(ctx, stream)
+        step(True)
+        lv.graph_end(ctx, stream)
+    for rep in range(3):
+        for x in (rgb, weight, tau, dd):
+            x.fill_(-7.0)
+        prune.fill_(9)
+        torch.cuda.synchronize()
+        lv.graph_launch(ctx, stream)
+        got = snap()
+        for a, b in zip(got[:8], eager[:8]):
+            assert torch.equal(a, b), f"replay {rep}"
+        for a, b in zip(got[8:], eager[8:]):
+            assert rel_l2(a.cpu().numpy(), b.cpu().numpy()) < 1e-5
+        _ = (torch.randn(1000, device=dev) * 2).sum().item()           # eager work between replays
+    lv.graph_reset(ctx)
+
+
 def test_autotune_returns_a_runnable_setting(ctx, tmp_path):
     import paper_2511_02510_amd as lv
     scene = small_shell(20000, seed=28, lmin=5, lmax=9)
