@@ -9,5 +9,5 @@ any of the method.
 from .scenes import (  # noqa: F401
     Scene, Camera, CONFIGS, make_config, make_scene_grid, make_scene_shell,
     make_cameras_single, make_cameras_ring, make_cameras_hemisphere,
-    make_target, scene_subset, config_seed,
+    make_target, scene_subset, config_seed, grid_points,
 )

@@ -281,6 +281,29 @@ def scene_subset(scene: Scene, idx) -> Scene:
 # target images
 # ----------------------------------------------------------------------------
 
+def grid_points(scene: Scene):
+    """Shared corner points of a leaf set (grid-point storage): corner c of
+    leaf v (c = x + 2y + 4z bits) lies at the finest-level coordinate
+    (ijk + bits) * 2^(L_MAX - l); leaves whose corners coincide share one
+    point (a corner in the middle of a coarser leaf's face or edge is a point
+    of its own).  Returns (corner_idx int32 [8][N], n_grid), points numbered
+    in the order of their first appearance."""
+    n = scene.n
+    shift = (L_MAX - scene.level.astype(np.int64))
+    keys = np.empty((8, n), dtype=np.int64)
+    for c in range(8):
+        x = (scene.ijk[0].astype(np.int64) + (c & 1)) << shift
+        y = (scene.ijk[1].astype(np.int64) + ((c >> 1) & 1)) << shift
+        z = (scene.ijk[2].astype(np.int64) + ((c >> 2) & 1)) << shift
+        keys[c] = x | (y << 13) | (z << 26)
+    flat = keys.T.ravel()                       # voxel-major: first appearance order
+    uniq, first, inv = np.unique(flat, return_index=True, return_inverse=True)
+    rank = np.empty(uniq.shape[0], dtype=np.int64)
+    rank[np.argsort(first, kind="stable")] = np.arange(uniq.shape[0])
+    idx = rank[inv].reshape(n, 8).T
+    return np.ascontiguousarray(idx, dtype=np.int32), int(uniq.shape[0])
+
+
 def make_target(rng: np.random.Generator, width: int, height: int) -> np.ndarray:
     """float32 [3, H, W]: 0.5 + six low-frequency sinusoids (at most 4 cycles
     per image, amplitude 0.08) + three half-plane steps (amplitude 0.25) per
