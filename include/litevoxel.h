@@ -84,7 +84,19 @@ typedef struct {
   int32_t width, height;
 } lv_camera;
 
-/* Sparse voxel leaves, structure of arrays in device memory. */
+/* Density activations (applied to each stored value before the trilinear
+ * interpolation, so a voxel's density stays trilinear). */
+#define LV_ACT_NONE 0
+#define LV_ACT_SOFTPLUS 1  /* log(1 + e^x) */
+#define LV_ACT_EXP 2       /* e^x */
+
+/* Sparse voxel leaves, structure of arrays in device memory.
+ * Dense layout (corner_idx NULL): density [8][n] holds one value per voxel
+ * corner.  Grid-point layout (the storage of the sparse-voxel rasterizer the
+ * paper starts from, Sec. III): density [n_grid] holds values on shared
+ * corner points and corner c of voxel v reads density[corner_idx[c n + v]];
+ * an index outside [0, n_grid) reads a corner density of 0.  Either way
+ * corner c of voxel v has density act(value), act = density_act. */
 typedef struct {
   int64_t n;               /* number of leaves */
   int32_t sh_degree;       /* 0..3 */
@@ -92,8 +104,11 @@ typedef struct {
   float root_size;         /* edge of the root cell */
   const uint16_t* ijk;     /* [3][n] integer cell coordinates at the leaf's level */
   const uint8_t* level;    /* [n] octree level (<= 12) */
-  const float* density;    /* [8][n] corner densities, corner c = x + 2y + 4z bits */
+  const float* density;    /* [8][n] corner values, corner c = x + 2y + 4z bits, or [n_grid] */
   const float* sh;         /* [3 (deg+1)^2][n], row (i*3 + channel), i = l*l + l + m */
+  const int32_t* corner_idx;  /* [8][n] grid point of each corner, or NULL (dense layout) */
+  int64_t n_grid;          /* grid points (grid-point layout only) */
+  int32_t density_act;     /* LV_ACT_* */
 } lv_voxels;
 
 /* A batch of views rendered in one call.  Pixel buffers pack the views in
@@ -153,8 +168,11 @@ lv_status lv_forward(lv_context* ctx, const lv_voxels* vox, const lv_frame* fram
 /* ----------------------------------------------------------------- backward
  * Adjoint of eq. 2-4 (and of the trilinear opacity and SH colour models):
  * given dL/d(rgb) [3P] and optional dL/d(depth), dL/d(alpha) [P] (NULL =
- * zero), writes dL/d(density) [8][n] and dL/d(sh) [3 (deg+1)^2][n]
- * (overwritten).  Transmittance is recomputed back to front from the state
+ * zero), writes dL/d(density) and dL/d(sh) [3 (deg+1)^2][n] (overwritten).
+ * dL/d(density) has the layout of vox->density: [8][n] for the dense layout,
+ * [n_grid] for grid points (each point sums the gradients of the corners
+ * that read it), with respect to the stored values (through the
+ * activation).  Transmittance is recomputed back to front from the state
  * lv_forward left in the workspace (same vox/frame/settings/workspace). */
 lv_status lv_backward(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
                       const lv_settings* st, void* workspace, const float* d_rgb,
@@ -275,7 +293,10 @@ lv_status lv_prune_guard(lv_context* ctx, const lv_voxels* vox, const lv_frame* 
  *    ijk = 2 ijk + bits, level + 1), whose corner densities are the parent's
  *    trilinear field at their corners (midpoints 0.5 a + 0.5 b along x,
  *    then y, then z: the density field is unchanged) and whose SH are the
- *    parent's.  Flags on leaves at LV_MAX_LEVEL are ignored.  n_needed
+ *    parent's.  Flags on leaves at LV_MAX_LEVEL are ignored.  Dense layout only
+ *    (LV_ERR_UNSUPPORTED for grid points); the midpoints refine the stored
+ *    values, so with a density activation other than LV_ACT_NONE the
+ *    children's field approximates the parent's instead of reproducing it.  n_needed
  *    (device u64, nullable) receives n + 7 (#split); rows at or beyond n_out
  *    are not written, so a wrong n_out gives a truncated set, never a write
  *    out of bounds.  The output arrays must not alias the input.

@@ -26,7 +26,11 @@ class LvCamera(ctypes.Structure):
 class LvVoxels(ctypes.Structure):
     _fields_ = [("n", c_int64), ("sh_degree", c_int32), ("root_min", c_float * 3),
                 ("root_size", c_float), ("ijk", c_void_p), ("level", c_void_p),
-                ("density", c_void_p), ("sh", c_void_p)]
+                ("density", c_void_p), ("sh", c_void_p), ("corner_idx", c_void_p),
+                ("n_grid", c_int64), ("density_act", c_int32)]
+
+
+ACT_NONE, ACT_SOFTPLUS, ACT_EXP = 0, 1, 2
 
 
 class LvFrame(ctypes.Structure):

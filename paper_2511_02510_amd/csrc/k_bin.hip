@@ -157,7 +157,9 @@ __device__ __forceinline__ uint32_t spread3_6(uint32_t x) {
   return x;
 }
 
-template <int DEG>
+// GENERIC: grid-point layout or a density activation; otherwise the dense
+// corner values are read as they are
+template <int DEG, bool GENERIC>
 __global__ __launch_bounds__(kBinBlock) void k_preprocess(RasterArgs a) {
   constexpr int NB = (DEG + 1) * (DEG + 1);
   __shared__ uint32_t s_tab[kTileWin];
@@ -176,7 +178,7 @@ __global__ __launch_bounds__(kBinBlock) void k_preprocess(RasterArgs a) {
   b[2] = a.root_min[2] + float(iz) * e;
   float sg[8];
 #pragma unroll
-  for (int c = 0; c < 8; ++c) sg[c] = a.density[c * n + i];
+  for (int c = 0; c < 8; ++c) sg[c] = GENERIC ? corner_density(a, c, i) : a.density[c * n + i];
   VoxRec vr;
   vr.be = make_float4(b[0], b[1], b[2], e);
   vr.s0 = make_float4(sg[0], sg[1], sg[2], sg[3]);
@@ -322,12 +324,15 @@ __global__ __launch_bounds__(kBinBlock) void k_preprocess(RasterArgs a) {
 hipError_t launch_preprocess(const RasterArgs& a, hipStream_t s) {
   const uint32_t blocks = uint32_t((a.n + kBinBlock - 1) / kBinBlock);
   if (blocks == 0) return hipSuccess;
+  const bool generic = a.corner_idx != nullptr || a.act != LV_ACT_NONE;
+#define LV_PRE(D) (generic ? k_preprocess<D, true> : k_preprocess<D, false>)
   switch (a.deg) {
-    case 0: hipLaunchKernelGGL(k_preprocess<0>, dim3(blocks), dim3(kBinBlock), 0, s, a); break;
-    case 1: hipLaunchKernelGGL(k_preprocess<1>, dim3(blocks), dim3(kBinBlock), 0, s, a); break;
-    case 2: hipLaunchKernelGGL(k_preprocess<2>, dim3(blocks), dim3(kBinBlock), 0, s, a); break;
-    default: hipLaunchKernelGGL(k_preprocess<3>, dim3(blocks), dim3(kBinBlock), 0, s, a); break;
+    case 0: hipLaunchKernelGGL(LV_PRE(0), dim3(blocks), dim3(kBinBlock), 0, s, a); break;
+    case 1: hipLaunchKernelGGL(LV_PRE(1), dim3(blocks), dim3(kBinBlock), 0, s, a); break;
+    case 2: hipLaunchKernelGGL(LV_PRE(2), dim3(blocks), dim3(kBinBlock), 0, s, a); break;
+    default: hipLaunchKernelGGL(LV_PRE(3), dim3(blocks), dim3(kBinBlock), 0, s, a); break;
   }
+#undef LV_PRE
   return hipGetLastError();
 }
 

@@ -2,8 +2,11 @@
 // stopped at the clamp at zero by the composite pass) are taken through the
 // SH expansion to the SH coefficients, summed over views, and the
 // voxel-major corner-density gradient the composite pass accumulated is
-// transposed into the caller's [8][n] rows.  One thread per voxel; the
-// output rows are written coalesced and fully overwritten.
+// taken through the density activation to the stored values: transposed
+// into the caller's [8][n] rows (dense layout), or added to the shared grid
+// points the corners read (grid-point layout, one atomic per corner).  One
+// thread per voxel; the dense rows are written coalesced and fully
+// overwritten.
 #include "lv_common.h"
 
 namespace lv {
@@ -13,10 +16,15 @@ hipError_t launch_bwd_setup(const RasterArgs& a, hipStream_t s) {
   if (e != hipSuccess) return e;
   e = launch_fill_u32(reinterpret_cast<uint32_t*>(a.ws.dcol), 3ull * uint64_t(a.n) * uint64_t(a.V), 0u, s);
   if (e != hipSuccess) return e;
+  if (a.corner_idx) {   // grid points accumulate the gradients of the corners that read them
+    e = launch_fill_u32(reinterpret_cast<uint32_t*>(a.d_density), uint64_t(a.n_grid), 0u, s);
+    if (e != hipSuccess) return e;
+  }
   return launch_fill_u32(a.ws.counters + C_QBWD, uint64_t(kQueues) * kQueueStride, 0u, s);
 }
 
-template <int DEG>
+// GENERIC: grid-point layout or a density activation
+template <int DEG, bool GENERIC>
 __global__ __launch_bounds__(256) void k_sh_bwd(RasterArgs a) {
   constexpr int NB = (DEG + 1) * (DEG + 1);
   const int64_t n = a.n;
@@ -26,8 +34,23 @@ __global__ __launch_bounds__(256) void k_sh_bwd(RasterArgs a) {
     const float4 d0 = reinterpret_cast<const float4*>(a.ws.dden)[2 * i];
     const float4 d1 = reinterpret_cast<const float4*>(a.ws.dden)[2 * i + 1];
     const float dd[8] = {d0.x, d0.y, d0.z, d0.w, d1.x, d1.y, d1.z, d1.w};
+    if (!GENERIC) {
 #pragma unroll
-    for (int c = 0; c < 8; ++c) a.d_density[size_t(c) * size_t(n) + size_t(i)] = dd[c];
+      for (int c = 0; c < 8; ++c) a.d_density[size_t(c) * size_t(n) + size_t(i)] = dd[c];
+    } else if (!a.corner_idx) {
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const size_t k = size_t(c) * size_t(n) + size_t(i);
+        a.d_density[k] = dd[c] * density_act_grad(a.density[k], a.act);
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const int64_t k = corner_slot(a, c, i);
+        if (k >= 0 && dd[c] != 0.0f)
+          unsafeAtomicAdd(&a.d_density[k], dd[c] * density_act_grad(a.density[k], a.act));
+      }
+    }
   }
   float acc[NB][3];
 #pragma unroll
@@ -63,12 +86,15 @@ __global__ __launch_bounds__(256) void k_sh_bwd(RasterArgs a) {
 hipError_t launch_sh_bwd(const RasterArgs& a, hipStream_t s) {
   const uint32_t blocks = uint32_t((a.n + 255) / 256);
   if (blocks == 0) return hipSuccess;
+  const bool generic = a.corner_idx != nullptr || a.act != LV_ACT_NONE;
+#define LV_SHB(D) (generic ? k_sh_bwd<D, true> : k_sh_bwd<D, false>)
   switch (a.deg) {
-    case 0: hipLaunchKernelGGL(k_sh_bwd<0>, dim3(blocks), dim3(256), 0, s, a); break;
-    case 1: hipLaunchKernelGGL(k_sh_bwd<1>, dim3(blocks), dim3(256), 0, s, a); break;
-    case 2: hipLaunchKernelGGL(k_sh_bwd<2>, dim3(blocks), dim3(256), 0, s, a); break;
-    default: hipLaunchKernelGGL(k_sh_bwd<3>, dim3(blocks), dim3(256), 0, s, a); break;
+    case 0: hipLaunchKernelGGL(LV_SHB(0), dim3(blocks), dim3(256), 0, s, a); break;
+    case 1: hipLaunchKernelGGL(LV_SHB(1), dim3(blocks), dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL(LV_SHB(2), dim3(blocks), dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL(LV_SHB(3), dim3(blocks), dim3(256), 0, s, a); break;
   }
+#undef LV_SHB
   return hipGetLastError();
 }
 

@@ -132,9 +132,13 @@ lv_status check_voxels(lv_context* ctx, const lv_voxels* vx, bool need_params) {
   if (!finite_pos(vx->root_size)) return fail(ctx, LV_ERR_ARG, "root_size must be finite and > 0");
   for (int k = 0; k < 3; ++k)
     if (!std::isfinite(vx->root_min[k])) return fail(ctx, LV_ERR_ARG, "non-finite root_min");
+  if (vx->density_act < LV_ACT_NONE || vx->density_act > LV_ACT_EXP)
+    return fail(ctx, LV_ERR_ARG, "density_act=%d is not an LV_ACT_* value", vx->density_act);
+  if (vx->corner_idx && (vx->n_grid < 0 || vx->n_grid > int64_t(0x7FFFFFFF)))
+    return fail(ctx, LV_ERR_ARG, "n_grid=%lld outside [0, 2^31)", (long long)vx->n_grid);
   if (vx->n > 0) {
     if (!vx->ijk || !vx->level) return fail(ctx, LV_ERR_ARG, "ijk/level must be non-NULL");
-    if (need_params && (!vx->density || !vx->sh))
+    if (need_params && (!vx->sh || (!vx->density && (!vx->corner_idx || vx->n_grid > 0))))
       return fail(ctx, LV_ERR_ARG, "density/sh must be non-NULL");
   }
   return LV_OK;
@@ -178,6 +182,9 @@ lv::RasterArgs make_args(const lv::Layout& L, void* ws, const lv_voxels* vx, con
   a.level = vx->level;
   a.density = vx->density;
   a.sh = vx->sh;
+  a.corner_idx = vx->corner_idx;
+  a.n_grid = vx->corner_idx ? vx->n_grid : 0;
+  a.act = vx->density_act;
   if (fr) {   // calls that need no views pass none
     a.V = fr->n_views;
     a.cams = fr->cams_dev;
@@ -574,6 +581,8 @@ lv_status lv_subdivide_apply(lv_context* ctx, const lv_voxels* vox, const uint8_
   if (!ctx) return LV_ERR_ARG;
   lv_status s = check_voxels(ctx, vox, true);
   if (s != LV_OK) return s;
+  if (vox->corner_idx)
+    return fail(ctx, LV_ERR_UNSUPPORTED, "subdivision needs the dense corner layout");
   if (n_out < vox->n || n_out > 8 * vox->n)
     return fail(ctx, LV_ERR_ARG, "n_out must lie in [n, 8 n]");
   if (!workspace || (vox->n > 0 && (!split || !ijk || !level || !density || !sh)))

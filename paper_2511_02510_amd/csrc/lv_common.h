@@ -194,6 +194,9 @@ struct RasterArgs {
   const uint8_t* level;
   const float* density;
   const float* sh;
+  const int32_t* corner_idx;   // grid-point layout, or null (dense)
+  int64_t n_grid;
+  int act;                     // LV_ACT_*
   // frame
   int V;
   const lv_camera* cams;
@@ -238,6 +241,32 @@ __device__ __forceinline__ float voxel_footprint(const RasterArgs& a, int64_t i)
     if (z > 0.0f) delta = fminf(delta, z / c.fx);
   }
   return delta;
+}
+
+// Density activation applied to each stored value (LV_ACT_*) and its
+// derivative.
+__device__ __forceinline__ float density_act(float x, int act) {
+  if (act == LV_ACT_SOFTPLUS) return x > 20.0f ? x : log1pf(expf(x));
+  if (act == LV_ACT_EXP) return expf(x);
+  return x;
+}
+__device__ __forceinline__ float density_act_grad(float x, int act) {
+  if (act == LV_ACT_SOFTPLUS) return 1.0f / (1.0f + expf(-x));
+  if (act == LV_ACT_EXP) return expf(x);
+  return 1.0f;
+}
+
+// Stored value behind corner c of voxel i: its index into a.density, or -1
+// when a grid index lies outside [0, n_grid) (the corner then reads 0).
+__device__ __forceinline__ int64_t corner_slot(const RasterArgs& a, int c, int64_t i) {
+  if (!a.corner_idx) return int64_t(c) * a.n + i;
+  const int64_t g = a.corner_idx[int64_t(c) * a.n + i];
+  return (g >= 0 && g < a.n_grid) ? g : int64_t(-1);
+}
+
+__device__ __forceinline__ float corner_density(const RasterArgs& a, int c, int64_t i) {
+  const int64_t k = corner_slot(a, c, i);
+  return k < 0 ? 0.0f : density_act(a.density[k], a.act);
 }
 
 // first pair of tile t (tile t + 1's start is its end), clipped to capacity

@@ -65,15 +65,22 @@ class Context:
 
 
 class Voxels:
-    """Voxel leaves in device memory (structure of arrays)."""
+    """Voxel leaves in device memory (structure of arrays).  Dense layout:
+    density [8, n], one value per corner.  Grid-point layout: density
+    [n_grid] on shared corner points and corner_idx [8, n] (int32); act is
+    the density activation (_abi.ACT_*) applied to every stored value."""
 
     def __init__(self, ijk: torch.Tensor, level: torch.Tensor, density: torch.Tensor,
-                 sh: torch.Tensor, root_min, root_size: float, sh_degree: int):
+                 sh: torch.Tensor, root_min, root_size: float, sh_degree: int,
+                 corner_idx: Optional[torch.Tensor] = None, act: int = 0):
         self.ijk, self.level, self.density, self.sh = ijk, level, density, sh
+        self.corner_idx = corner_idx
+        self.act = int(act)
         self.root_min = [float(x) for x in root_min]
         self.root_size = float(root_size)
         self.sh_degree = int(sh_degree)
         self.n = int(level.shape[0])
+        self.n_grid = int(density.shape[0]) if corner_idx is not None else 0
         self.struct = self._make(density, sh)
 
     def _make(self, density, sh) -> LvVoxels:
@@ -84,8 +91,11 @@ class Voxels:
         s.root_size = self.root_size
         s.ijk = self.ijk.data_ptr() if self.n else None
         s.level = self.level.data_ptr() if self.n else None
-        s.density = density.data_ptr() if self.n else None
+        s.density = density.data_ptr() if density.numel() else None
         s.sh = sh.data_ptr() if self.n else None
+        s.corner_idx = self.corner_idx.data_ptr() if (self.corner_idx is not None and self.n) else None
+        s.n_grid = self.n_grid
+        s.density_act = self.act
         return s
 
     def with_params(self, density: torch.Tensor, sh: torch.Tensor) -> "Voxels":
@@ -96,13 +106,26 @@ class Voxels:
         return v
 
     @staticmethod
-    def from_scene(scene, device) -> "Voxels":
+    def from_grid(scene, corner_idx, grid_values, device, act: int = 0) -> "Voxels":
+        """The leaves of `scene` with grid-point densities: corner_idx [8, n],
+        grid_values [n_grid] (the scene's own density rows are not used)."""
+        dev = torch.device(device)
+        ijk = torch.from_numpy(np.ascontiguousarray(scene.ijk).view(np.int16)).to(dev)
+        level = torch.from_numpy(np.ascontiguousarray(scene.level)).to(dev)
+        idx = torch.from_numpy(np.ascontiguousarray(corner_idx, dtype=np.int32)).to(dev)
+        vals = torch.from_numpy(np.ascontiguousarray(grid_values, dtype=np.float32)).to(dev)
+        sh = torch.from_numpy(np.ascontiguousarray(scene.sh, dtype=np.float32)).to(dev)
+        return Voxels(ijk, level, vals, sh, scene.root_min, scene.root_size, scene.sh_degree,
+                      corner_idx=idx, act=act)
+
+    @staticmethod
+    def from_scene(scene, device, act: int = 0) -> "Voxels":
         dev = torch.device(device)
         ijk = torch.from_numpy(np.ascontiguousarray(scene.ijk).view(np.int16)).to(dev)
         level = torch.from_numpy(np.ascontiguousarray(scene.level)).to(dev)
         dens = torch.from_numpy(np.ascontiguousarray(scene.density, dtype=np.float32)).to(dev)
         sh = torch.from_numpy(np.ascontiguousarray(scene.sh, dtype=np.float32)).to(dev)
-        return Voxels(ijk, level, dens, sh, scene.root_min, scene.root_size, scene.sh_degree)
+        return Voxels(ijk, level, dens, sh, scene.root_min, scene.root_size, scene.sh_degree, act=act)
 
 
 class Frame:
@@ -310,7 +333,7 @@ def subdivide_apply(ctx, vox, split, n_out, workspace, n_needed=None, stream=Non
     ctx.check(ctx.lib.lv_subdivide_apply(ctx.h, ctypes.byref(vox.struct), _p(split), n_out,
                                          _p(workspace), _p(ijk), _p(level), _p(dens), _p(sh),
                                          _p(n_needed), _stream(stream)), "lv_subdivide_apply")
-    return Voxels(ijk, level, dens, sh, vox.root_min, vox.root_size, vox.sh_degree)
+    return Voxels(ijk, level, dens, sh, vox.root_min, vox.root_size, vox.sh_degree, act=vox.act)
 
 
 def graph_begin(ctx, stream):

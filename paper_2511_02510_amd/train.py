@@ -131,7 +131,7 @@ class Trainer:
         n_pruned = int(n - int(keep.sum()))
         vox = lv.Voxels(self.vox.ijk[:, keep].contiguous(), self.vox.level[keep].contiguous(),
                         self.density.data[:, keep].contiguous(), self.sh.data[:, keep].contiguous(),
-                        self.vox.root_min, self.vox.root_size, self.vox.sh_degree)
+                        self.vox.root_min, self.vox.root_size, self.vox.sh_degree, act=self.vox.act)
         ema, state, useful = self.ema[keep], self.state[keep], self.useful[keep]
         frame = self.frame
         # subdivision of the kept voxels by their usefulness
