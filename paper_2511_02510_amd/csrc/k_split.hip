@@ -148,7 +148,6 @@ struct SplitOut {
   float* density;    // [8][m]
   float* sh;         // [K][m]
   int64_t m;         // output size
-  uint64_t* needed;  // n + 7 (#split), nullable
 };
 
 // Each block takes kSplitPer voxels in order; a voxel's output position is
@@ -236,7 +235,7 @@ hipError_t run_split_apply(const RasterArgs& a, const uint8_t* split, int64_t m,
                      needed);
   if (nb > 0) {
     SplitOut o;
-    o.ijk = ijk; o.level = level; o.density = density; o.sh = sh; o.m = m; o.needed = needed;
+    o.ijk = ijk; o.level = level; o.density = density; o.sh = sh; o.m = m;
     const int K = 3 * (a.deg + 1) * (a.deg + 1);
     hipLaunchKernelGGL(k_split_write, dim3(nb), dim3(kSplitPer), 0, s, a, split, (const uint32_t*)pre,
                        K, o);

@@ -9,7 +9,7 @@ that pairs lv_forward with lv_backward.
 from __future__ import annotations
 
 import ctypes
-from typing import List, Optional, Sequence
+from typing import Optional, Sequence
 
 import numpy as np
 import torch

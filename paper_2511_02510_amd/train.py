@@ -19,7 +19,7 @@ import dataclasses
 import json
 import math
 import time
-from typing import Dict, List, Optional
+from typing import Dict, List
 
 import numpy as np
 import torch
