@@ -250,8 +250,10 @@ def test_graph_replays_match_eager(ctx):
         torch.cuda.synchronize()
         lv.graph_launch(ctx, stream)
         got = snap()
-        for a, b in zip(got[:5], eager[:5]):
+        for a, b in zip(got[:4], eager[:4]):          # rgb, depth, alpha, w_max: deterministic
             assert torch.equal(a, b), f"replay {rep}"
+        # the loss sums block partials with atomics, in scheduling order
+        assert torch.allclose(got[4], eager[4], rtol=1e-6, atol=0.0), f"replay {rep}"
         for a, b in zip(got[5:], eager[5:]):
             assert rel_l2(a.cpu().numpy(), b.cpu().numpy()) < 1e-5
         _ = (torch.randn(1000, device=dev) * 2).sum().item()           # eager work between replays
@@ -341,8 +343,11 @@ def test_two_stream_graph_matches_eager(ctx):
         torch.cuda.synchronize()
         lv.graph_launch(ctx, stream)
         got = snap()
-        for a, b in zip(got[:8], eager[:8]):
-            assert torch.equal(a, b), f"replay {rep}"
+        for i in (0, 1, 2, 3, 6, 7):                  # rgb, depth, alpha, w_max, tau, prune
+            assert torch.equal(got[i], eager[i]), f"replay {rep}, output {i}"
+        # the loss and the weight normalisation sum block partials with atomics
+        for i in (4, 5):
+            assert torch.allclose(got[i], eager[i], rtol=1e-6, atol=0.0), f"replay {rep}, output {i}"
         for a, b in zip(got[8:], eager[8:]):
             assert rel_l2(a.cpu().numpy(), b.cpu().numpy()) < 1e-5
         _ = (torch.randn(1000, device=dev) * 2).sum().item()           # eager work between replays
