@@ -217,7 +217,8 @@ def main():
     ap.add_argument("--tile", type=int, default=0, help="0 = autotune")
     ap.add_argument("--chunk", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-views", type=int, default=1)
+    ap.add_argument("--cpu-sample-views", type=int, default=8,
+                    help="views of the workload the oracle baseline renders (8 = the whole step)")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="if > 0: only run this many eager steps (for rocprofv3) and exit")
     ap.add_argument("--other-workloads", default="grid4k,shell200k,shell200k_train,hemi4m",
