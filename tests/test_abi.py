@@ -99,6 +99,25 @@ def test_validation_rejects_bad_arguments():
     assert v() == _abi.LV_ERR_ARG
     fr._keep[0].fx = 50.0
     assert lib.lv_validate(None, ctypes.byref(fr), ctypes.byref(st)) == _abi.LV_ERR_ARG
+    # grid-point layout and density activation fields
+    for bad in (-1, 3):
+        vox.density_act = bad
+        assert v() == _abi.LV_ERR_ARG, bad
+    vox.density_act = _abi.ACT_SOFTPLUS
+    assert v() == _abi.LV_OK
+    vox.corner_idx = 0x2000
+    vox.n_grid = -1
+    assert v() == _abi.LV_ERR_ARG
+    vox.n_grid = 1 << 31
+    assert v() == _abi.LV_ERR_ARG
+    vox.n_grid = 0                      # every corner index out of range: densities 0
+    vox.density = None
+    assert v() == _abi.LV_OK
+    vox.n_grid = 100
+    assert v() == _abi.LV_ERR_ARG       # values needed when there are grid points
+    vox.density = 0x1000
+    assert v() == _abi.LV_OK
+    vox.corner_idx, vox.n_grid, vox.density_act = None, 0, _abi.ACT_NONE
     # an empty scene is valid (background-only render)
     vox.n = 0
     vox.ijk = vox.level = vox.density = vox.sh = None
@@ -129,6 +148,11 @@ def test_aux_workspace_sizes():
     assert lib.lv_lf_weight_workspace_size(0) == 0
     assert lib.lv_quantile_workspace_size(1000, 16) >= 1000 * 9
     assert lib.lv_quantile_workspace_size(1000, 65) == 0
+    # guards and subdivision: keys (4 B) + flags (1 B) per voxel at least
+    for n in (0, 1000, 1 << 20):
+        assert lib.lv_guard_workspace_size(n) >= 5 * n
+        assert lib.lv_split_workspace_size(n) >= 5 * n
+    assert lib.lv_guard_workspace_size(-1) == 0 and lib.lv_split_workspace_size(-1) == 0
 
 
 @pytest.mark.parametrize("t", [0, 1000, 5999, 6000, 9000, 11999, 12000, 15000, 20000])
