@@ -462,7 +462,9 @@ class Renderer:
 
 
 class RasterizeFn(torch.autograd.Function):
-    """(density [8,N], sh [K,N]) -> (rgb [3P], depth [P], alpha [P]).
+    """(density [8,N] or [n_grid] in the renderer's layout, sh [K,N]) ->
+    (rgb [3P], depth [P], alpha [P]); gradients with respect to the stored
+    density values (through the layout's activation) and the SH.
 
     The backward recomputes transmittance back to front inside lv_backward
     from the per-pixel state lv_forward left in the renderer's workspace

@@ -132,6 +132,35 @@ def test_out_of_range_indices_read_zero(ctx):
     _check(g, ref, ogrid.grid_gradient(dc, raw, idx, ogrid.ACT_SOFTPLUS), dsh)
 
 
+def test_autograd_through_the_grid_layout(ctx):
+    import paper_2511_02510_amd as lv
+    import torch
+    scene = small_shell(8000, seed=95, deg=1, lmin=5, lmax=8)
+    idx, ng = synth.grid_points(scene)
+    rng = np.random.default_rng(96)
+    raw = rng.normal(0.0, 1.0, ng).astype(np.float32)
+    vox = lv.Voxels.from_grid(scene, idx, raw, ctx.device, act=ogrid.ACT_SOFTPLUS)
+    frame = lv.Frame(CAMS, ctx.device)
+    r = lv.Renderer(ctx, vox, frame, lv.settings())
+    P = frame.P
+    g_rgb = to_dev(rng.normal(0, 1e-3, 3 * P), ctx.device)
+    g_alpha = to_dev(rng.normal(0, 1e-3, P), ctx.device)
+    say("autograd through the grid layout")
+    density = vox.density.clone().requires_grad_(True)
+    sh = vox.sh.clone().requires_grad_(True)
+    wmax = torch.zeros(vox.n, device=ctx.device)
+    rgb, depth, alpha = lv.rasterize(density, sh, r, wmax)
+    ((rgb * g_rgb).sum() + (alpha * g_alpha).sum()).backward()
+    dd = torch.empty_like(vox.density)
+    dsh = torch.empty_like(vox.sh)
+    r.forward(*r.new_outputs(), torch.zeros(vox.n, device=ctx.device))
+    r.backward(g_rgb, None, g_alpha, dd, dsh)
+    torch.cuda.synchronize()
+    assert density.grad.shape == (ng,)
+    assert rel_l2(density.grad.cpu().numpy(), dd.cpu().numpy()) <= 1e-5
+    assert rel_l2(sh.grad.cpu().numpy(), dsh.cpu().numpy()) <= 1e-5
+
+
 def test_grid_layout_argument_errors(ctx):
     import paper_2511_02510_amd as lv
     import torch
