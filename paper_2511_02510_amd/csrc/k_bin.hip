@@ -32,7 +32,34 @@ __device__ int32_t split_threshold(float o, float root_min, float root_size) {
   return lo;
 }
 
+// Grid-stride fill of n words with v by the threads tid = 0, stride, ...:
+// 16-byte stores over the aligned middle, single words at the ends.
+__device__ __forceinline__ void fill_words(uint32_t* p, uint64_t n, uint32_t v, uint64_t tid,
+                                           uint64_t stride) {
+  const uint64_t head = ((16u - (reinterpret_cast<uintptr_t>(p) & 15u)) & 15u) / 4u;   // words to 16-B alignment
+  const uint64_t h = head < n ? head : n;
+  if (tid < h) p[tid] = v;
+  const uint64_t nv = (n - h) / 4;
+  uint4* q = reinterpret_cast<uint4*>(p + h);
+  const uint4 vv = make_uint4(v, v, v, v);
+  for (uint64_t i = tid; i < nv; i += stride) q[i] = vv;
+  const uint64_t t0 = h + 4 * nv;
+  if (tid < n - t0) p[t0 + tid] = v;
+}
+
+static uint32_t fill_blocks(uint64_t n) {
+  uint64_t blocks = (n / 4 + 255) / 256;
+  if (blocks < 1) blocks = 1;
+  if (blocks > 8192) blocks = 8192;
+  return uint32_t(blocks);
+}
+
+// Every block zeroes its share of the per-(sub-counter, tile) counts; block 0
+// also clears the counters and builds the view table.
 __global__ void k_setup(RasterArgs a) {
+  fill_words(a.ws.tcount, uint64_t(a.T) * kSpread + 1, 0u,
+             uint64_t(blockIdx.x) * blockDim.x + threadIdx.x, uint64_t(gridDim.x) * blockDim.x);
+  if (blockIdx.x != 0) return;
   const int t = threadIdx.x;
   for (int k = t; k < kCounterWords; k += blockDim.x) a.ws.counters[k] = 0u;
   for (int v = t; v < a.V; v += blockDim.x)
@@ -57,32 +84,34 @@ __global__ void k_setup(RasterArgs a) {
 }
 
 hipError_t launch_setup(const RasterArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_setup, dim3(1), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_setup, dim3(fill_blocks(uint64_t(a.T) * kSpread + 1)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
-// Fills n words with v: 16-byte stores over the aligned middle, single words
-// at the ends.  A graph-safe replacement for a memset.
+// Fills n words with v (a graph-safe replacement for a memset).
 __global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
-  const uint64_t tid = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
-  const uint64_t head = ((16u - (reinterpret_cast<uintptr_t>(p) & 15u)) & 15u) / 4u;   // words to 16-B alignment
-  const uint64_t h = head < n ? head : n;
-  if (tid < h) p[tid] = v;
-  const uint64_t nv = (n - h) / 4;
-  uint4* q = reinterpret_cast<uint4*>(p + h);
-  const uint4 vv = make_uint4(v, v, v, v);
-  for (uint64_t i = tid; i < nv; i += stride) q[i] = vv;
-  const uint64_t t0 = h + 4 * nv;
-  if (tid < n - t0) p[t0 + tid] = v;
+  fill_words(p, n, v, uint64_t(blockIdx.x) * blockDim.x + threadIdx.x,
+             uint64_t(gridDim.x) * blockDim.x);
+}
+
+// Up to kFillRanges fills in one launch (blockIdx.y = range).
+__global__ void k_fill_set(FillSet f) {
+  const int r = blockIdx.y;
+  fill_words(f.p[r], f.n[r], f.v[r], uint64_t(blockIdx.x) * blockDim.x + threadIdx.x,
+             uint64_t(gridDim.x) * blockDim.x);
+}
+
+hipError_t launch_fill_set(const FillSet& f, hipStream_t s) {
+  if (f.count <= 0) return hipSuccess;
+  uint64_t most = 0;
+  for (int r = 0; r < f.count; ++r) most = f.n[r] > most ? f.n[r] : most;
+  hipLaunchKernelGGL(k_fill_set, dim3(fill_blocks(most), uint32_t(f.count)), dim3(256), 0, s, f);
+  return hipGetLastError();
 }
 
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  uint64_t blocks = (n / 4 + 255) / 256;
-  if (blocks < 1) blocks = 1;
-  if (blocks > 8192) blocks = 8192;
-  hipLaunchKernelGGL(k_fill_u32, dim3(uint32_t(blocks)), dim3(256), 0, s, p, n, v);
+  hipLaunchKernelGGL(k_fill_u32, dim3(fill_blocks(n)), dim3(256), 0, s, p, n, v);
   return hipGetLastError();
 }
 

@@ -12,15 +12,20 @@
 namespace lv {
 
 hipError_t launch_bwd_setup(const RasterArgs& a, hipStream_t s) {
-  hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(a.ws.dden), 8ull * uint64_t(a.n), 0u, s);
-  if (e != hipSuccess) return e;
-  e = launch_fill_u32(reinterpret_cast<uint32_t*>(a.ws.dcol), 3ull * uint64_t(a.n) * uint64_t(a.V), 0u, s);
-  if (e != hipSuccess) return e;
-  if (a.corner_idx) {   // grid points accumulate the gradients of the corners that read them
-    e = launch_fill_u32(reinterpret_cast<uint32_t*>(a.d_density), uint64_t(a.n_grid), 0u, s);
-    if (e != hipSuccess) return e;
-  }
-  return launch_fill_u32(a.ws.counters + C_QBWD, uint64_t(kQueues) * kQueueStride, 0u, s);
+  FillSet f;
+  f.count = 0;
+  auto add = [&f](void* p, uint64_t n) {
+    f.p[f.count] = static_cast<uint32_t*>(p);
+    f.n[f.count] = n;
+    f.v[f.count] = 0u;
+    ++f.count;
+  };
+  add(a.ws.dden, 8ull * uint64_t(a.n));
+  add(a.ws.dcol, 3ull * uint64_t(a.n) * uint64_t(a.V));
+  add(a.ws.counters + C_QBWD, uint64_t(kQueues) * kQueueStride);
+  // grid points accumulate the gradients of the corners that read them
+  if (a.corner_idx) add(a.d_density, uint64_t(a.n_grid));
+  return launch_fill_set(f, s);
 }
 
 // GENERIC: grid-point layout or a density activation

@@ -287,9 +287,7 @@ lv_status lv_forward(lv_context* ctx, const lv_voxels* vox, const lv_frame* fram
   a.wmax = wmax;
   {
     PhaseTimer t(ctx, LV_PH_SETUP, stream);
-    LV_TRY(lv::launch_setup(a, stream), "setup");
-    LV_TRY(lv::launch_fill_u32(a.ws.tcount, uint64_t(L.T) * lv::kSpread + 1, 0u, stream),
-           "fill tile counts");
+    LV_TRY(lv::launch_setup(a, stream), "setup");   // also zeroes the tile counts
   }
   {
     PhaseTimer t(ctx, LV_PH_PREPROCESS, stream);

@@ -327,6 +327,14 @@ __device__ __forceinline__ void sh_basis(float x, float y, float z, float* Y) {
 // (defined in the kernel translation units)
 hipError_t launch_setup(const RasterArgs& a, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
+constexpr int kFillRanges = 4;
+struct FillSet {   // word ranges filled by one launch
+  uint32_t* p[kFillRanges];
+  uint64_t n[kFillRanges];
+  uint32_t v[kFillRanges];
+  int count;
+};
+hipError_t launch_fill_set(const FillSet& f, hipStream_t s);
 hipError_t launch_preprocess(const RasterArgs& a, hipStream_t s);
 hipError_t launch_scan_tiles(const RasterArgs& a, uint32_t nblk, hipStream_t s);
 hipError_t launch_emit(const RasterArgs& a, hipStream_t s);
