@@ -111,8 +111,11 @@ def training_step(lv, ctx, r, vox, frame, target, gamma, form, bufs, stream, sid
     """One step: forward, loss weight, L1 gradient, backward (+ depth quantile).
     With overlap the loss weight (it needs only the target and gamma) runs on
     `side` beside the forward, and the depth quantile (it needs only w_max)
-    beside the backward; events join the two streams, also inside a captured
-    graph.  Without overlap everything runs in order on `stream`."""
+    beside the L1 gradient; events join the two streams, also inside a
+    captured graph.  The backward waits for the quantile: run beside the
+    backward, whose persistent workgroups fill every CU, the quantile's
+    kernels slow it by more than they take alone.  Without overlap
+    everything runs in order on `stream`."""
     import torch
     rgb, depth, alpha, wmax, weight, lw_ws, loss, d_rgb, dd, dsh, nb, q_ws, tau, prune = bufs
     aux = side if overlap else stream
@@ -129,20 +132,20 @@ def training_step(lv, ctx, r, vox, frame, target, gamma, form, bufs, stream, sid
         e_f = torch.cuda.Event()
         e_f.record(stream)
         stream.wait_event(e_w)
-    lv.l1_grad(ctx, frame, rgb, target, weight, loss, d_rgb, stream=stream)
     if quantile and overlap:
         side.wait_event(e_f)
         lv.depth_quantile(ctx, vox, frame, wmax, nb, 0.1, q_ws, tau, prune, stream=side)
         e_q = torch.cuda.Event()
         e_q.record(side)
+    lv.l1_grad(ctx, frame, rgb, target, weight, loss, d_rgb, stream=stream)
+    if quantile and overlap:
+        stream.wait_event(e_q)
     r.backward(d_rgb, None, None, dd, dsh, stream=stream)
     if quantile and not overlap:
         lv.depth_quantile(ctx, vox, frame, wmax, nb, 0.1, q_ws, tau, prune, stream=stream)
-    if quantile and overlap:
-        stream.wait_event(e_q)
 
 
-def measure_workload(lv, ctx, name, tile, chunk, reps, warmup, quantile, form, gamma):
+def measure_workload(lv, ctx, name, tile, chunk, chunk_bwd, reps, warmup, quantile, form, gamma):
     """Forward and whole-step MP/s of another named workload (graph replay)."""
     import torch
     import synth
@@ -154,7 +157,7 @@ def measure_workload(lv, ctx, name, tile, chunk, reps, warmup, quantile, form, g
     frame = lv.Frame(cams, dev)
     P = frame.P
     target = torch.from_numpy(np.concatenate([t.ravel() for t in targets]).astype(np.float32)).to(dev)
-    r = lv.Renderer(ctx, vox, frame, lv.settings(tile=tile, chunk=chunk))
+    r = lv.Renderer(ctx, vox, frame, lv.settings(tile=tile, chunk=chunk, chunk_bwd=chunk_bwd))
     rgb, depth, alpha = r.new_outputs()
     wmax = torch.zeros(vox.n, device=dev)
     weight = torch.empty(P, device=dev)
@@ -215,7 +218,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="ring1m")
     ap.add_argument("--tile", type=int, default=0, help="0 = autotune")
-    ap.add_argument("--chunk", type=int, default=64)
+    ap.add_argument("--chunk", type=int, default=64, help="forward chunk (with --tile)")
+    ap.add_argument("--chunk-bwd", type=int, default=0, help="backward chunk (0 = --chunk)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-views", type=int, default=8,
                     help="views of the workload the oracle baseline renders (8 = the whole step)")
@@ -262,11 +266,14 @@ def main():
 
     if args.tile == 0:
         best, table = lv.autotune(ctx, vox, frame, reps=3)
-        st = lv.settings(tile=best.tile, chunk=best.chunk, pair_capacity=best.pair_capacity)
-        log(f"[bench] autotune fwd+bwd ms (tile 8/16/32 x chunk 64/128/256):\n{np.round(table, 3)}")
+        st = lv.settings(tile=best.tile, chunk=best.chunk, chunk_bwd=best.chunk_bwd,
+                         pair_capacity=best.pair_capacity)
+        log(f"[bench] autotune ms (forward, backward; tile 8/16/32 x chunk 64/128/256):\n"
+            f"{np.round(table, 3)}")
     else:
-        st = lv.settings(tile=args.tile, chunk=args.chunk)
-    log(f"[bench] settings tile={st.tile} chunk={st.chunk}")
+        st = lv.settings(tile=args.tile, chunk=args.chunk, chunk_bwd=args.chunk_bwd)
+    chunk_bwd = int(st.chunk_bwd) or int(st.chunk)
+    log(f"[bench] settings tile={st.tile} chunk={st.chunk} chunk_bwd={chunk_bwd}")
 
     r = lv.Renderer(ctx, vox, frame, st)
     rgb, depth, alpha = r.new_outputs()
@@ -318,7 +325,7 @@ def main():
     log("[bench] phase ms/launch: " + ", ".join(f"{k} {v:.3f}" for k, v in phases.items()))
 
     # ---- graph capture of one whole step (loss weight and depth quantile on
-    # a second stream beside the forward and the backward)
+    # a second stream beside the forward and the L1 gradient)
     lv.graph_begin(ctx, stream)
     step(overlap=True)
     lv.graph_end(ctx, stream)
@@ -353,7 +360,7 @@ def main():
     single = []
     for v, c in enumerate(cams):
         f1 = lv.Frame([c], dev)
-        r1 = lv.Renderer(ctx, vox, f1, lv.settings(tile=st.tile, chunk=st.chunk))
+        r1 = lv.Renderer(ctx, vox, f1, lv.settings(tile=st.tile, chunk=st.chunk, chunk_bwd=chunk_bwd))
         o = r1.new_outputs()
         w1 = torch.empty(f1.P, device=dev)
         lw1 = torch.empty(lv.lf_weight_workspace_size(1), dtype=torch.uint8, device=dev)
@@ -386,8 +393,9 @@ def main():
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
             "alg_bytes_per_launch": int(alg), "ms_per_launch": round(phases[dom], 4)}
-    roof["traffic"] = counter_traffic(dom, int(st.tile), int(st.chunk))
-    roof["valu"] = counter_valu(dom, int(st.tile), int(st.chunk), phases[dom])
+    dom_chunk = chunk_bwd if dom == "composite_bwd" else int(st.chunk)
+    roof["traffic"] = counter_traffic(dom, int(st.tile), dom_chunk)
+    roof["valu"] = counter_valu(dom, int(st.tile), dom_chunk, phases[dom])
     fwd_alg = composite_bytes(Q, P, "composite_fwd")
     fwd_roof = fwd_alg / (phases["composite_fwd"] * 1e-3) / 1e9
 
@@ -469,7 +477,7 @@ def main():
     for name in [w for w in args.other_workloads.split(",") if w]:
         spec = {"grid4k": (False, 0, 0.5), "shell200k": (False, 1, 0.5),
                 "shell200k_train": (False, 1, 0.5), "hemi4m": (True, 0, 0.5)}[name]
-        others[name] = measure_workload(lv, ctx, name, int(st.tile), int(st.chunk),
+        others[name] = measure_workload(lv, ctx, name, int(st.tile), int(st.chunk), chunk_bwd,
                                         max(3, args.steps // 2), 2, *spec)
 
     # ---- CPU baseline: the oracle on a bounded sample (the first views)
@@ -517,9 +525,10 @@ def main():
         "config": {"workload": f"{args.workload}: {scene.n} voxels (octree levels 7-11, shell + 10% "
                                f"clutter), SH degree 3, {len(cams)} ring views "
                                f"{[(c.width, c.height) for c in cams]}, {P} px per step",
-                   "tile": int(st.tile), "chunk": int(st.chunk), "pairs": int(Q),
+                   "tile": int(st.tile), "chunk": int(st.chunk), "chunk_bwd": chunk_bwd,
+                   "pairs": int(Q),
                    "streams": "render and gradient on one stream; loss weight beside the forward "
-                              "and depth quantile beside the backward on a second (one graph)"},
+                              "and depth quantile beside the L1 gradient on a second (one graph)"},
         "roofline": roof,
         "cpu_baseline": cpu,
         "fwd_mp_s": round(P / fwd_ms / 1e3, 2),

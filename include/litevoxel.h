@@ -124,7 +124,8 @@ typedef struct {
 
 typedef struct {
   int32_t tile;            /* tile side in pixels: 8, 16 or 32 */
-  int32_t chunk;           /* voxels staged in LDS per step: 64, 128 or 256 */
+  int32_t chunk;           /* voxels staged in LDS per step of the forward: 64, 128 or 256 */
+  int32_t chunk_bwd;       /* the same for the backward; 0 = chunk */
   float t_eps;             /* a ray stops once T < t_eps (0 < t_eps <= 1e-5) */
   uint64_t pair_capacity;  /* capacity of the (tile, voxel) pair buffers */
 } lv_settings;
@@ -141,7 +142,7 @@ lv_status lv_create(lv_context** out, int hip_device);   /* sets the device curr
 void lv_destroy(lv_context* ctx);
 const char* lv_status_str(lv_status s);
 const char* lv_last_error(const lv_context* ctx);        /* "" if none; ctx may be NULL */
-void lv_default_settings(lv_settings* s);                 /* tile 16, chunk 64, t_eps 1e-6 */
+void lv_default_settings(lv_settings* s);   /* tile 16, chunk 64, chunk_bwd 0, t_eps 1e-6 */
 
 /* Host-only argument checks (no device access): LV_OK or LV_ERR_ARG. */
 lv_status lv_validate(const lv_voxels* vox, const lv_frame* frame, const lv_settings* st);
@@ -333,11 +334,14 @@ lv_status lv_graph_end(lv_context* ctx, hipStream_t stream);
 lv_status lv_graph_launch(lv_context* ctx, hipStream_t stream);
 lv_status lv_graph_reset(lv_context* ctx);
 
-/* Autotuner: times forward+backward for every tile in {8,16,32} x chunk in
- * {64,128,256} on these inputs (device memory it needs is allocated and freed
- * inside; synchronises) and writes the fastest into *best (capacity sized
- * for that tile).  ms_table (nullable) receives 9 fwd+bwd times in ms,
- * tile-major; a configuration that cannot run gets a negative entry. */
+/* Autotuner: times the forward and the backward separately for every tile in
+ * {8,16,32} x chunk in {64,128,256} on these inputs (device memory it needs
+ * is allocated and freed inside; synchronises) and writes into *best the
+ * tile whose fastest forward plus fastest backward is smallest, with those
+ * two chunks as chunk and chunk_bwd (capacity sized for that tile).
+ * ms_table (nullable) receives 18 times in ms: 9 forward times, tile-major
+ * over the chunks, then the 9 backward times in the same order; a
+ * configuration that cannot run gets a negative entry. */
 lv_status lv_autotune(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
                       int32_t reps, lv_settings* best, float* ms_table, hipStream_t stream);
 

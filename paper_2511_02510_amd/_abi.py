@@ -39,7 +39,7 @@ class LvFrame(ctypes.Structure):
 
 
 class LvSettings(ctypes.Structure):
-    _fields_ = [("tile", c_int32), ("chunk", c_int32), ("t_eps", c_float),
+    _fields_ = [("tile", c_int32), ("chunk", c_int32), ("chunk_bwd", c_int32), ("t_eps", c_float),
                 ("pair_capacity", c_uint64)]
 
 

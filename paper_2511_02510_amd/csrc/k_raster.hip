@@ -129,17 +129,24 @@ __device__ __forceinline__ void build_masks(const Stage<CH>& S, Masks<TS, CH>& M
   const int nwords = int((nc + 63) / 64);
   for (int w = 0; w < nwords; ++w) {
     const int j = w * 64 + lane;
-    const int ylo = int(S.yr[j] & 0xFFFFu) - toy, yhi = int(S.yr[j] >> 16) - toy;
-    const int xlo = int(S.xr[j] & 0xFFFFu) - tox, xhi = int(S.xr[j] >> 16) - tox;
+    int ylo = int(S.yr[j] & 0xFFFFu) - toy, yhi = int(S.yr[j] >> 16) - toy;
+    int xlo = int(S.xr[j] & 0xFFFFu) - tox, xhi = int(S.xr[j] >> 16) - tox;
+    const uint32_t ys = yhi >= ylo ? uint32_t(yhi - ylo) : 0u;
+    const uint32_t xs = xhi >= xlo ? uint32_t(xhi - xlo) : 0u;
+    ylo = yhi >= ylo ? ylo : -0x10000;
+    xlo = xhi >= xlo ? xlo : -0x10000;
+    unsigned long long br = 0, bc = 0;
 #pragma unroll
     for (int k = 0; k < RPW; ++k) {
       const int r = wave * RPW + k;
-      const unsigned long long br = __ballot(r >= ylo && r <= yhi);
-      const unsigned long long bc = __ballot(r >= xlo && r <= xhi);
-      if (lane == k) {
-        M.rows[w][r] = br;
-        M.cols[w][r] = bc;
-      }
+      const unsigned long long yb = __builtin_amdgcn_ballot_w64(uint32_t(r - ylo) <= ys);
+      const unsigned long long xb = __builtin_amdgcn_ballot_w64(uint32_t(r - xlo) <= xs);
+      br = lane == k ? yb : br;
+      bc = lane == k ? xb : bc;
+    }
+    if (lane < RPW) {
+      M.rows[w][wave * RPW + lane] = br;
+      M.cols[w][wave * RPW + lane] = bc;
     }
   }
 }
@@ -217,25 +224,39 @@ __device__ __forceinline__ float opacity(float tau, float ex) {
 __device__ __forceinline__ int pix_x_of_lane(int lane) { return ((lane >> 4) & 1) * 4 + (lane & 3); }
 __device__ __forceinline__ int pix_y_of_lane(int lane) { return (lane >> 5) * 4 + ((lane >> 2) & 3); }
 
-template <int K>
-__device__ __forceinline__ float row_shr(float v) {   // lanes with no source read 0
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x110 + K, 0xF, 0xF, false));
-}
+// One step of the scan over 11 values: v += (lane - K of the same row) * f,
+// with f = 1 where that lane lies in this lane's run and 0 elsewhere, as one
+// fused multiply-add per value that reads the shifted operand through DPP
+// (lanes with no source in the row keep v).  The leading and trailing s_nop
+// give the two wait states a DPP read needs after a VALU write of its
+// operand, on both sides of the block.  Every lane of the wave must be active.
+#define LV_SEG_FMAC(K, R) "v_fmac_f32_dpp %" #R ", %" #R ", %11 row_shr:" #K " row_mask:0xf bank_mask:0xf\n"
+#define LV_SEG_BLOCK(K)                                                                     \
+  "s_nop 1\n" LV_SEG_FMAC(K, 0) LV_SEG_FMAC(K, 1) LV_SEG_FMAC(K, 2) LV_SEG_FMAC(K, 3)         \
+      LV_SEG_FMAC(K, 4) LV_SEG_FMAC(K, 5) LV_SEG_FMAC(K, 6) LV_SEG_FMAC(K, 7) LV_SEG_FMAC(K, 8) \
+          LV_SEG_FMAC(K, 9) LV_SEG_FMAC(K, 10) "s_nop 1"
 
-template <int K, int NV>
+template <int K>
 __device__ __forceinline__ void seg_step(float* v, int dist) {
   if (__ballot(dist >= K) == 0) return;
-#pragma unroll
-  for (int c = 0; c < NV; ++c) {
-    const float t = row_shr<K>(v[c]);
-    v[c] = dist >= K ? v[c] + t : v[c];
-  }
+  const float f = dist >= K ? 1.0f : 0.0f;
+#define LV_SEG_ASM(K)                                                                          \
+  asm volatile(LV_SEG_BLOCK(K)                                                                 \
+               : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]), "+v"(v[4]), "+v"(v[5]),       \
+                 "+v"(v[6]), "+v"(v[7]), "+v"(v[8]), "+v"(v[9]), "+v"(v[10])                   \
+               : "v"(f))
+  if constexpr (K == 1) LV_SEG_ASM(1);
+  else if constexpr (K == 2) LV_SEG_ASM(2);
+  else if constexpr (K == 4) LV_SEG_ASM(4);
+  else LV_SEG_ASM(8);
+#undef LV_SEG_ASM
 }
+#undef LV_SEG_BLOCK
+#undef LV_SEG_FMAC
 
 // After the call, a lane with `last` set holds in v the sum over its run of
 // lanes with the same key (pend lanes only; others form runs of their own).
-template <int NV>
-__device__ __forceinline__ bool seg_reduce_rows(float* v, int jj, bool pend) {
+__device__ __forceinline__ bool seg_reduce_rows(float (&v)[11], int jj, bool pend) {
   const int lane = threadIdx.x & 63;
   const int key = pend ? jj : -1 - lane;
   const int prev = __builtin_amdgcn_update_dpp(0x7FFFFFFF, key, 0x111, 0xF, 0xF, false);
@@ -245,10 +266,10 @@ __device__ __forceinline__ bool seg_reduce_rows(float* v, int jj, bool pend) {
   if (H != ~0ull) {
     const unsigned long long le = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
     const int dist = lane - (63 - __builtin_clzll(H & le));
-    seg_step<1, NV>(v, dist);
-    seg_step<2, NV>(v, dist);
-    seg_step<4, NV>(v, dist);
-    seg_step<8, NV>(v, dist);
+    seg_step<1>(v, dist);
+    seg_step<2>(v, dist);
+    seg_step<4>(v, dist);
+    seg_step<8>(v, dist);
   }
   return last;
 }
@@ -531,7 +552,7 @@ __device__ __forceinline__ void bwd_drain(const Stage<CH>& S, const BwdRing<CH>&
     const float gc[3] = {R.gc[p][0], R.gc[p][1], R.gc[p][2]};
     bwd_spread(S, jj, d, R.gh[e], R.wk[e], gc, R.tm[e], R.hl[e], g);
   }
-  const bool last = seg_reduce_rows<11>(g, jj, valid);
+  const bool last = seg_reduce_rows(g, jj, valid);
   if (valid && last) {
 #pragma unroll
     for (int c = 0; c < 11; ++c) atomicAdd(&s_g[c][jj], double(g[c]));
@@ -630,9 +651,10 @@ __global__ __launch_bounds__(TS* TS) void k_composite_bwd(RasterArgs a) {
         for (;;) {
           const bool act = m != 0;
           if (__ballot(act) == 0) break;
+          // jj and the fragment values are read only where hit is set
           bool hit = false;
-          int jj = 0;
-          float gh = 0.0f, wk = 0.0f, tm = 0.0f, hl = 0.0f;
+          int jj;
+          float gh, wk, tm, hl;
           if (act) {
             const int jbit = 63 - __builtin_clzll(m);
             m &= ~(1ull << jbit);

@@ -150,6 +150,8 @@ lv_status check_settings(lv_context* ctx, const lv_settings* st) {
     return fail(ctx, LV_ERR_ARG, "tile=%d not in {8, 16, 32}", st->tile);
   if (st->chunk != 64 && st->chunk != 128 && st->chunk != 256)
     return fail(ctx, LV_ERR_ARG, "chunk=%d not in {64, 128, 256}", st->chunk);
+  if (st->chunk_bwd != 0 && st->chunk_bwd != 64 && st->chunk_bwd != 128 && st->chunk_bwd != 256)
+    return fail(ctx, LV_ERR_ARG, "chunk_bwd=%d not in {0, 64, 128, 256}", st->chunk_bwd);
   if (!(st->t_eps > 0.0f) || !(st->t_eps <= 1e-5f))
     return fail(ctx, LV_ERR_ARG, "t_eps=%g outside (0, 1e-5]", double(st->t_eps));
   if (st->pair_capacity >= (uint64_t(1) << 32))
@@ -226,6 +228,7 @@ void lv_default_settings(lv_settings* s) {
   if (!s) return;
   s->tile = 16;
   s->chunk = 64;
+  s->chunk_bwd = 0;
   s->t_eps = 1e-6f;
   s->pair_capacity = 0;
 }
@@ -341,7 +344,8 @@ lv_status lv_backward(lv_context* ctx, const lv_voxels* vox, const lv_frame* fra
   }
   {
     PhaseTimer t(ctx, LV_PH_COMPOSITE_BWD, stream);
-    LV_TRY(lv::launch_composite_bwd(a, st->chunk, 0, stream), "composite backward");
+    LV_TRY(lv::launch_composite_bwd(a, st->chunk_bwd ? st->chunk_bwd : st->chunk, 0, stream),
+           "composite backward");
   }
   {
     PhaseTimer t(ctx, LV_PH_SH_BWD, stream);
@@ -675,7 +679,7 @@ lv_status lv_autotune(lv_context* ctx, const lv_voxels* vox, const lv_frame* fra
         *dd = nullptr, *dsh = nullptr;
   void* ws = nullptr;
   size_t ws_bytes = 0;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
   lv_status result = LV_OK;
   float best_ms = -1.0f;
   auto cleanup = [&]() {
@@ -683,15 +687,16 @@ lv_status lv_autotune(lv_context* ctx, const lv_voxels* vox, const lv_frame* fra
                     static_cast<void*>(wmax), static_cast<void*>(drgb), static_cast<void*>(dd),
                     static_cast<void*>(dsh), ws})
       if (p) (void)hipFree(p);
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
+    for (hipEvent_t e : {e0, e1, e2})
+      if (e) (void)hipEventDestroy(e);
   };
   bool ok = hipMalloc(&rgb, 12 * P) == hipSuccess && hipMalloc(&depth, 4 * P) == hipSuccess &&
             hipMalloc(&alpha, 4 * P) == hipSuccess && hipMalloc(&drgb, 12 * P) == hipSuccess &&
             hipMalloc(&wmax, 4 * size_t(n > 0 ? n : 1)) == hipSuccess &&
             hipMalloc(&dd, 32 * size_t(n > 0 ? n : 1)) == hipSuccess &&
             hipMalloc(&dsh, 4 * size_t(nb) * size_t(n > 0 ? n : 1)) == hipSuccess &&
-            hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+            hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess &&
+            hipEventCreate(&e2) == hipSuccess;
   if (!ok) { cleanup(); return fail(ctx, LV_ERR_HIP, "autotune: allocation failed"); }
   // a small non-zero upstream gradient so the backward does its full work
   if (lv::launch_fill_u32(reinterpret_cast<uint32_t*>(drgb), 3 * P, 0x358637bdu /* 1e-6f */, stream) != hipSuccess ||
@@ -724,25 +729,41 @@ lv_status lv_autotune(lv_context* ctx, const lv_voxels* vox, const lv_frame* fra
       cap = std::min<uint64_t>(needed + needed / 16 + 1024, 0xFFFFFFFFull);
     }
     if (result != LV_OK) break;
+    // the forward's per-pixel results do not depend on the chunk, so the
+    // backward can be repeated on any forward's workspace
+    float fwd_ms[3], bwd_ms[3];
     for (int ci = 0; ci < 3; ++ci) {
       st.chunk = chunks[ci];
-      float ms = 0.0f;
-      // warm-up, then timed repetitions of forward + backward
-      bool run_ok = true;
-      for (int r = -1; r < reps && run_ok; ++r) {
-        if (r == 0 && hipEventRecord(e0, stream) != hipSuccess) { run_ok = false; break; }
-        run_ok = lv_forward(ctx, vox, frame, &st, ws, rgb, depth, alpha, wmax, stream) == LV_OK &&
-                 lv_backward(ctx, vox, frame, &st, ws, drgb, nullptr, nullptr, dd, dsh, stream) == LV_OK;
+      st.chunk_bwd = chunks[ci];
+      float mf = 0.0f, mb = 0.0f;
+      bool run_ok = lv_forward(ctx, vox, frame, &st, ws, rgb, depth, alpha, wmax, stream) == LV_OK &&
+                    lv_backward(ctx, vox, frame, &st, ws, drgb, nullptr, nullptr, dd, dsh, stream) == LV_OK &&
+                    hipEventRecord(e0, stream) == hipSuccess;
+      for (int r = 0; r < reps && run_ok; ++r)
+        run_ok = lv_forward(ctx, vox, frame, &st, ws, rgb, depth, alpha, wmax, stream) == LV_OK;
+      run_ok = run_ok && hipEventRecord(e1, stream) == hipSuccess;
+      for (int r = 0; r < reps && run_ok; ++r)
+        run_ok = lv_backward(ctx, vox, frame, &st, ws, drgb, nullptr, nullptr, dd, dsh, stream) == LV_OK;
+      run_ok = run_ok && hipEventRecord(e2, stream) == hipSuccess && hipEventSynchronize(e2) == hipSuccess &&
+               hipEventElapsedTime(&mf, e0, e1) == hipSuccess && hipEventElapsedTime(&mb, e1, e2) == hipSuccess;
+      fwd_ms[ci] = run_ok ? mf / reps : -1.0f;
+      bwd_ms[ci] = run_ok ? mb / reps : -1.0f;
+      if (ms_table) {
+        ms_table[ti * 3 + ci] = fwd_ms[ci];
+        ms_table[9 + ti * 3 + ci] = bwd_ms[ci];
       }
-      if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) run_ok = false;
-      if (run_ok && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) run_ok = false;
-      ms = run_ok ? ms / reps : -1.0f;
-      if (ms_table) ms_table[ti * 3 + ci] = ms;
-      if (run_ok && (best_ms < 0.0f || ms < best_ms)) {
-        best_ms = ms;
-        *best = st;
-        best->pair_capacity = std::min<uint64_t>(needed + needed / 16 + 1024, 0xFFFFFFFFull);
-      }
+    }
+    int bf = -1, bb = -1;
+    for (int ci = 0; ci < 3; ++ci) {
+      if (fwd_ms[ci] >= 0.0f && (bf < 0 || fwd_ms[ci] < fwd_ms[bf])) bf = ci;
+      if (bwd_ms[ci] >= 0.0f && (bb < 0 || bwd_ms[ci] < bwd_ms[bb])) bb = ci;
+    }
+    if (bf >= 0 && bb >= 0 && (best_ms < 0.0f || fwd_ms[bf] + bwd_ms[bb] < best_ms)) {
+      best_ms = fwd_ms[bf] + bwd_ms[bb];
+      *best = st;
+      best->chunk = chunks[bf];
+      best->chunk_bwd = chunks[bb];
+      best->pair_capacity = std::min<uint64_t>(needed + needed / 16 + 1024, 0xFFFFFFFFull);
     }
   }
   ctx->timing = was_timing;

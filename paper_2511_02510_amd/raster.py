@@ -171,9 +171,12 @@ class Frame:
         return rgb[3 * self.off[v]:3 * self.off[v + 1]].view(3, h, w)
 
 
-def settings(tile=16, chunk=64, t_eps=1e-6, pair_capacity=0) -> LvSettings:
+def settings(tile=16, chunk=64, t_eps=1e-6, pair_capacity=0, chunk_bwd=0) -> LvSettings:
+    """chunk: voxels staged per step of the forward; chunk_bwd: of the
+    backward (0: the same as chunk)."""
     s = LvSettings()
-    s.tile, s.chunk, s.t_eps, s.pair_capacity = int(tile), int(chunk), float(t_eps), int(pair_capacity)
+    s.tile, s.chunk, s.chunk_bwd = int(tile), int(chunk), int(chunk_bwd)
+    s.t_eps, s.pair_capacity = float(t_eps), int(pair_capacity)
     return s
 
 
@@ -362,10 +365,12 @@ def tune_key(vox, frame) -> str:
 
 
 def autotune(ctx, vox, frame, reps=3, t_eps=1e-6, stream=None, cache=None):
-    """-> (best LvSettings, ms table [3 tiles x 3 chunks]).
+    """-> (best LvSettings, ms table [forward, backward] x 3 tiles x 3 chunks).
 
+    The best setting takes the tile whose fastest forward plus fastest
+    backward is smallest, and those two chunks as chunk and chunk_bwd.
     cache: optional path of a JSON file of earlier results keyed by tune_key;
-    a hit returns the stored tile and chunk (pair capacity 0: the Renderer
+    a hit returns the stored tile and chunks (pair capacity 0: the Renderer
     plans it) without timing anything, a miss times and stores."""
     import json
     import os
@@ -373,22 +378,24 @@ def autotune(ctx, vox, frame, reps=3, t_eps=1e-6, stream=None, cache=None):
     if cache is not None and os.path.exists(cache):
         with open(cache) as fh:
             known = json.load(fh)
-        if key in known:
-            hit = known[key]
-            return (settings(tile=int(hit["tile"]), chunk=int(hit["chunk"]), t_eps=t_eps),
-                    np.array(hit["ms_table"], dtype=np.float64).reshape(3, 3))
+        hit = known.get(key)
+        if hit is not None and "chunk_bwd" in hit and len(hit["ms_table"]) == 18:
+            return (settings(tile=int(hit["tile"]), chunk=int(hit["chunk"]), t_eps=t_eps,
+                             chunk_bwd=int(hit["chunk_bwd"])),
+                    np.array(hit["ms_table"], dtype=np.float64).reshape(2, 3, 3))
     best = settings(t_eps=t_eps)
-    table = (ctypes.c_float * 9)()
+    table = (ctypes.c_float * 18)()
     ctx.check(ctx.lib.lv_autotune(ctx.h, ctypes.byref(vox.struct), ctypes.byref(frame.struct),
                                   int(reps), ctypes.byref(best), ctypes.cast(table, ctypes.c_void_p),
                                   _stream(stream)), "lv_autotune")
-    ms = np.array(list(table), dtype=np.float64).reshape(3, 3)
+    ms = np.array(list(table), dtype=np.float64).reshape(2, 3, 3)
     if cache is not None:
         known = {}
         if os.path.exists(cache):
             with open(cache) as fh:
                 known = json.load(fh)
         known[key] = {"tile": int(best.tile), "chunk": int(best.chunk),
+                      "chunk_bwd": int(best.chunk_bwd),
                       "ms_table": [round(float(x), 4) for x in ms.ravel()]}
         tmp = f"{cache}.tmp{os.getpid()}"
         with open(tmp, "w") as fh:

@@ -30,14 +30,15 @@ def to_dev(a, dev, dtype=np.float32):
 
 
 def run_gpu(ctx, scene, cams, tile=16, chunk=64, bg=(0.0, 0.0, 0.0), cap=0, grads=None,
-            export=True, wmax_in=None):
+            export=True, wmax_in=None, chunk_bwd=0):
     """Forward (+ backward when grads = (g_rgb, g_depth, g_alpha)) on the GPU."""
     import torch
     m = lv()
     dev = ctx.device
     vox = m.Voxels.from_scene(scene, dev)
     frame = m.Frame(cams, dev, bg)
-    r = m.Renderer(ctx, vox, frame, m.settings(tile=tile, chunk=chunk, pair_capacity=cap))
+    r = m.Renderer(ctx, vox, frame, m.settings(tile=tile, chunk=chunk, pair_capacity=cap,
+                                               chunk_bwd=chunk_bwd))
     rgb, depth, alpha = r.new_outputs()
     wmax = torch.zeros(max(vox.n, 1), device=dev) if wmax_in is None else to_dev(wmax_in, dev)
     r.forward(rgb, depth, alpha, wmax)

@@ -61,7 +61,7 @@ def _vox_frame(n=100, w=64, h=48, views=1):
 def test_default_settings_and_status_strings():
     lib = _abi.lib()
     _, _, st = _vox_frame()
-    assert (st.tile, st.chunk, st.pair_capacity) == (16, 64, 0)
+    assert (st.tile, st.chunk, st.chunk_bwd, st.pair_capacity) == (16, 64, 0, 0)
     assert abs(st.t_eps - 1e-6) < 1e-12
     for s in range(6):
         assert lib.lv_status_str(s)
@@ -73,7 +73,8 @@ def test_validation_rejects_bad_arguments():
     vox, fr, st = _vox_frame()
     v = lambda: lib.lv_validate(ctypes.byref(vox), ctypes.byref(fr), ctypes.byref(st))
     assert v() == _abi.LV_OK
-    for field, bad in [("tile", 12), ("chunk", 32), ("t_eps", 1e-3), ("t_eps", 0.0)]:
+    for field, bad in [("tile", 12), ("chunk", 32), ("chunk_bwd", 32), ("chunk_bwd", -64),
+                       ("t_eps", 1e-3), ("t_eps", 0.0)]:
         old = getattr(st, field)
         setattr(st, field, bad)
         assert v() == _abi.LV_ERR_ARG, field
@@ -177,7 +178,8 @@ def test_autotune_cache_key_and_hit_without_device(tmp_path):
     # the resolution multiset, not the view order, is part of the key
     assert lv.tune_key(vox, lv.Frame(cams[::-1], "cpu")) == key
     path = tmp_path / "tune.json"
-    path.write_text(json.dumps({key: {"tile": 8, "chunk": 128, "ms_table": list(range(9))}}))
+    path.write_text(json.dumps({key: {"tile": 8, "chunk": 128, "chunk_bwd": 64,
+                                      "ms_table": list(range(18))}}))
     best, table = lv.autotune(None, vox, frame, cache=str(path))
-    assert (best.tile, best.chunk, best.pair_capacity) == (8, 128, 0)
-    assert table.shape == (3, 3) and table[2, 2] == 8
+    assert (best.tile, best.chunk, best.chunk_bwd, best.pair_capacity) == (8, 128, 64, 0)
+    assert table.shape == (2, 3, 3) and table[0, 2, 2] == 8 and table[1, 0, 0] == 9

@@ -312,16 +312,16 @@ def test_two_stream_graph_matches_eager(ctx):
             e_f = torch.cuda.Event()
             e_f.record(stream)
             stream.wait_event(e_w)
-        lv.l1_grad(ctx, frame, rgb, tgt, weight, loss, d_rgb, stream=stream)
         if overlap:
             side.wait_event(e_f)
         lv.depth_quantile(ctx, vox, frame, wmax, 16, 0.1, qws, tau, prune, stream=aux)
         if overlap:
             e_q = torch.cuda.Event()
             e_q.record(side)
-        r.backward(d_rgb, None, None, dd, dsh, stream=stream)
+        lv.l1_grad(ctx, frame, rgb, tgt, weight, loss, d_rgb, stream=stream)
         if overlap:
             stream.wait_event(e_q)
+        r.backward(d_rgb, None, None, dd, dsh, stream=stream)
 
     def snap():
         torch.cuda.synchronize()
@@ -364,11 +364,16 @@ def test_autotune_returns_a_runnable_setting(ctx, tmp_path):
     cache = str(tmp_path / "tune.json")
     best, table = lv.autotune(ctx, vox, frame, reps=2, cache=cache)
     again, table2 = lv.autotune(ctx, vox, frame, reps=2, cache=cache)   # served by the cache
-    assert (again.tile, again.chunk) == (best.tile, best.chunk)
+    assert (again.tile, again.chunk, again.chunk_bwd) == (best.tile, best.chunk, best.chunk_bwd)
     assert np.allclose(table2, np.round(table, 4))
-    assert best.tile in (8, 16, 32) and best.chunk in (64, 128, 256)
-    assert np.all(table > 0)
-    assert abs(table.min() - table[[8, 16, 32].index(best.tile), [64, 128, 256].index(best.chunk)]) < 1e-9
+    assert best.tile in (8, 16, 32) and best.chunk in (64, 128, 256) and best.chunk_bwd in (64, 128, 256)
+    assert table.shape == (2, 3, 3) and np.all(table > 0)
+    # the chosen tile minimises fastest forward + fastest backward; the chunks are those minima
+    ti = [8, 16, 32].index(best.tile)
+    per_tile = table[0].min(axis=1) + table[1].min(axis=1)
+    assert abs(per_tile.min() - per_tile[ti]) < 1e-9
+    assert table[0, ti, [64, 128, 256].index(best.chunk)] == table[0, ti].min()
+    assert table[1, ti, [64, 128, 256].index(best.chunk_bwd)] == table[1, ti].min()
     g = run_gpu(ctx, scene, cams, tile=best.tile, chunk=best.chunk, cap=best.pair_capacity, export=False)
     ref = oracle.render(scene, cams)
     assert np.abs(g["rgb"] - ref["rgb"]).max() <= IMG_TOL

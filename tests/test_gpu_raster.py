@@ -172,13 +172,17 @@ def test_capacity_overflow_is_reported_and_replanned(ctx):
 
 
 # ------------------------------------------------------------- backward
-@pytest.mark.parametrize("tile,chunk", [(16, 64), (8, 256), (32, 128)])
-def test_backward_grid4k(ctx, tile, chunk):
+@pytest.mark.parametrize("tile,chunk,chunk_bwd", [(16, 64, 0), (8, 256, 0), (32, 128, 0),
+                                                  (16, 128, 64), (16, 64, 256)])
+def test_backward_grid4k(ctx, tile, chunk, chunk_bwd):
+    # chunk_bwd != chunk: the backward stages its lists with another chunk
+    # than the forward that left the per-pixel state
     scene, cams, _ = synth.make_config("grid4k")
     P = cams[0].npix
     grads = random_grads(np.random.default_rng(7), P)
-    say(f"backward grid4k tile={tile} chunk={chunk}")
-    g = run_gpu(ctx, scene, cams, tile=tile, chunk=chunk, grads=grads, export=False)
+    say(f"backward grid4k tile={tile} chunk={chunk} chunk_bwd={chunk_bwd}")
+    g = run_gpu(ctx, scene, cams, tile=tile, chunk=chunk, grads=grads, export=False,
+                chunk_bwd=chunk_bwd)
     dd, dsh = oracle.backward(scene, cams, *grads)
     e1, e2 = rel_l2(g["dd"], dd), rel_l2(g["dsh"], dsh)
     say(f"  rel L2: density {e1:.2e} sh {e2:.2e}")
