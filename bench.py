@@ -109,40 +109,45 @@ def step_bytes(N, M, Q, P, K):
 def training_step(lv, ctx, r, vox, frame, target, gamma, form, bufs, stream, side, quantile,
                   verify=False, overlap=True):
     """One step: forward, loss weight, L1 gradient, backward (+ depth quantile).
-    With overlap the loss weight (it needs only the target and gamma) runs on
-    `side` beside the forward, and the depth quantile (it needs only w_max)
-    beside the L1 gradient; events join the two streams, also inside a
-    captured graph.  The backward waits for the quantile: run beside the
-    backward, whose persistent workgroups fill every CU, the quantile's
-    kernels slow it by more than they take alone.  Without overlap
-    everything runs in order on `stream`."""
+    With overlap, work that does not need the forward runs on `side` beside
+    it: the loss weight (it needs only the target and gamma) and the depth
+    quantile's binning (it needs only the geometry); the quantile's cutoff
+    (it needs w_max) runs beside the L1 gradient.  Events join the two
+    streams, also inside a captured graph.  The backward waits for the
+    cutoff: run beside the backward, whose persistent workgroups fill every
+    CU, the quantile's kernels slow it by more than they take alone.
+    Without overlap everything runs in order on `stream`."""
     import torch
     rgb, depth, alpha, wmax, weight, lw_ws, loss, d_rgb, dd, dsh, nb, q_ws, tau, prune = bufs
-    aux = side if overlap else stream
-    if overlap:
-        e0 = torch.cuda.Event()
-        e0.record(stream)
-        side.wait_event(e0)
-    lv.lf_weight(ctx, frame, target, gamma, form, 1e-3, weight, lw_ws, stream=aux)
-    if overlap:
-        e_w = torch.cuda.Event()
-        e_w.record(side)
+    if not overlap:
+        lv.lf_weight(ctx, frame, target, gamma, form, 1e-3, weight, lw_ws, stream=stream)
+        r.forward(rgb, depth, alpha, wmax, stream=stream, verify=verify)
+        lv.l1_grad(ctx, frame, rgb, target, weight, loss, d_rgb, stream=stream)
+        r.backward(d_rgb, None, None, dd, dsh, stream=stream)
+        if quantile:
+            lv.depth_quantile(ctx, vox, frame, wmax, nb, 0.1, q_ws, tau, prune, stream=stream)
+        return
+    e0 = torch.cuda.Event()
+    e0.record(stream)
+    side.wait_event(e0)
+    lv.lf_weight(ctx, frame, target, gamma, form, 1e-3, weight, lw_ws, stream=side)
+    e_w = torch.cuda.Event()
+    e_w.record(side)
+    if quantile:
+        lv.depth_bins(ctx, vox, frame, nb, q_ws, stream=side)
     r.forward(rgb, depth, alpha, wmax, stream=stream, verify=verify)
-    if overlap:
-        e_f = torch.cuda.Event()
-        e_f.record(stream)
-        stream.wait_event(e_w)
-    if quantile and overlap:
+    e_f = torch.cuda.Event()
+    e_f.record(stream)
+    stream.wait_event(e_w)
+    if quantile:
         side.wait_event(e_f)
-        lv.depth_quantile(ctx, vox, frame, wmax, nb, 0.1, q_ws, tau, prune, stream=side)
+        lv.depth_cutoff(ctx, vox, wmax, nb, 0.1, q_ws, tau, prune, stream=side)
         e_q = torch.cuda.Event()
         e_q.record(side)
     lv.l1_grad(ctx, frame, rgb, target, weight, loss, d_rgb, stream=stream)
-    if quantile and overlap:
+    if quantile:
         stream.wait_event(e_q)
     r.backward(d_rgb, None, None, dd, dsh, stream=stream)
-    if quantile and not overlap:
-        lv.depth_quantile(ctx, vox, frame, wmax, nb, 0.1, q_ws, tau, prune, stream=stream)
 
 
 def measure_workload(lv, ctx, name, tile, chunk, chunk_bwd, reps, warmup, quantile, form, gamma):
@@ -527,8 +532,9 @@ def main():
                                f"{[(c.width, c.height) for c in cams]}, {P} px per step",
                    "tile": int(st.tile), "chunk": int(st.chunk), "chunk_bwd": chunk_bwd,
                    "pairs": int(Q),
-                   "streams": "render and gradient on one stream; loss weight beside the forward "
-                              "and depth quantile beside the L1 gradient on a second (one graph)"},
+                   "streams": "render and gradient on one stream; loss weight and the depth "
+                              "quantile's binning beside the forward, its cutoff beside the L1 "
+                              "gradient, on a second (one graph)"},
         "roofline": roof,
         "cpu_baseline": cpu,
         "fwd_mp_s": round(P / fwd_ms / 1e3, 2),

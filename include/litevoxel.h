@@ -28,7 +28,8 @@
  * voxel parameters, Sec. II-B).  lv_lf_weight / lv_l1_grad implement the
  * inverse-Sobel reweighted L1 photometric term (Sec. IV-B, eq. 7-10) and
  * lv_depth_quantile the depth-binned w_max quantile cutoff
- * (Sec. IV-C, eq. 11-12 with the eq. 14 depth normalisation).
+ * (Sec. IV-C, eq. 11-12 with the eq. 14 depth normalisation), also as the
+ * pair lv_depth_bins / lv_depth_cutoff.
  *
  * Conventions for every call:
  *   - Device pointers point to memory of the context's device, owned by the
@@ -233,6 +234,20 @@ uint64_t lv_quantile_workspace_size(int64_t n, int32_t n_bins);
 lv_status lv_depth_quantile(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
                             const float* wmax, int32_t n_bins, double q, void* workspace,
                             float* tau, uint8_t* prune, uint8_t* bins, hipStream_t stream);
+
+/* The same in two calls.  lv_depth_bins does the part that does not read
+ * w_max (delta, p5/p95, bins and per-bin counts, kept in the workspace;
+ * bins [n] also written when non-NULL), so it can run before or beside the
+ * forward pass; lv_depth_cutoff then computes tau and prune from w_max on
+ * that workspace.  The cutoff requires a workspace filled by lv_depth_bins
+ * for the same voxels and n_bins (it may be called again with other w_max
+ * values; otherwise its results are unspecified, but every access stays
+ * inside the workspace).  Results are identical to lv_depth_quantile's. */
+lv_status lv_depth_bins(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
+                        int32_t n_bins, void* workspace, uint8_t* bins, hipStream_t stream);
+lv_status lv_depth_cutoff(lv_context* ctx, const lv_voxels* vox, const float* wmax, int32_t n_bins,
+                          double q, void* workspace, float* tau, uint8_t* prune,
+                          hipStream_t stream);
 
 /* ------------------------------------------- pruning stability guards
  * One adaptation step of the three guards on pruning (Sec. IV-C, guards

@@ -78,6 +78,8 @@ _SIGS = {
     "lv_quantile_workspace_size": (c_uint64, [c_int64, c_int32]),
     "lv_depth_quantile": (c_int32, [P, POINTER(LvVoxels), POINTER(LvFrame), P, c_int32, c_double,
                                     P, P, P, P, P]),
+    "lv_depth_bins": (c_int32, [P, POINTER(LvVoxels), POINTER(LvFrame), c_int32, P, P, P]),
+    "lv_depth_cutoff": (c_int32, [P, POINTER(LvVoxels), P, c_int32, c_double, P, P, P, P]),
     "lv_default_guard": (None, [POINTER(LvGuardParams)]),
     "lv_guard_workspace_size": (c_uint64, [c_int64]),
     "lv_prune_guard": (c_int32, [P, POINTER(LvVoxels), POINTER(LvFrame), P, P, P, c_int32,

@@ -8,7 +8,9 @@
 //   4. tau_b = ceil(q |V_b|)-th smallest w_max of bin b (the generalised
 //      inverse of the bin's empirical CDF), prune = w_max <= tau_bin.
 // All selections are exact radix selects on device (p5 and p95 in the same
-// passes); nothing returns to the host.
+// passes); nothing returns to the host.  Steps 1-3 do not read w_max and run
+// as one call (the binning), step 4 as another (the cutoff) on the
+// binning's workspace, so the binning can run before the forward pass.
 #include "lv_common.h"
 #include "lv_select.h"
 
@@ -16,7 +18,6 @@ namespace lv {
 
 struct QuantWS {
   uint32_t* dkey;     // [n] keys of delta
-  uint32_t* wkey;     // [n] keys of w_max
   uint8_t* bins;      // [n]
   SelSet pct;         // p5 and p95 of delta (2 segments)
   SelSet bin;         // the quantile of w_max in each bin (B segments)
@@ -28,7 +29,7 @@ static size_t sel_bytes(int nseg) {
 }
 
 uint64_t quant_ws_bytes(int64_t n, int B) {
-  return align256(4 * size_t(n)) * 2 + align256(size_t(n)) + sel_bytes(2) + sel_bytes(B) +
+  return align256(4 * size_t(n)) + align256(size_t(n)) + sel_bytes(2) + sel_bytes(B) +
          align256(4 * size_t(B));
 }
 
@@ -44,7 +45,6 @@ static QuantWS quant_bind(void* base, int64_t n, int B) {
   char* b = static_cast<char*>(base);
   QuantWS w;
   w.dkey = reinterpret_cast<uint32_t*>(b); b += align256(4 * size_t(n));
-  w.wkey = reinterpret_cast<uint32_t*>(b); b += align256(4 * size_t(n));
   w.bins = reinterpret_cast<uint8_t*>(b); b += align256(size_t(n));
   b = sel_bind(b, 2, w.pct);
   b = sel_bind(b, B, w.bin);
@@ -62,23 +62,24 @@ __device__ __forceinline__ uint32_t rank_of(double q, uint32_t n) {
   return uint32_t(r) - 1u;
 }
 
-// block s < 2: percentile segment s; block 2 + b: bin b (its initial state
-// comes from the bin counts, in the first histogram pass; until then both
-// rows say "no answer", which is also the result when there are no voxels)
-__global__ void k_q_setup(QuantWS w, int B, uint32_t n) {
-  const int s = blockIdx.x;
-  const SelSet& S = s < 2 ? w.pct : w.bin;
-  const int sg = s < 2 ? s : s - 2;
+// part 0 (binning), block s < 2: percentile segment s, and the bin counts;
+// part 1 (cutoff), block b: bin b, whose initial state comes from the bin
+// counts in the first histogram pass.  Until then both rows say "no
+// answer", which is also the result when there are no voxels.
+__global__ void k_q_setup(QuantWS w, int B, uint32_t n, int part) {
+  const int sg = blockIdx.x;
+  const SelSet& S = part == 0 ? w.pct : w.bin;
   for (int pass = 0; pass < 4; ++pass) sel_hist(S, pass, sg)[threadIdx.x] = 0u;
+  if (part == 0 && sg == 0)
+    for (int k = threadIdx.x; k < B; k += blockDim.x) w.cnt[k] = 0u;
   if (threadIdx.x == 0) {
     SelState st;
     st.prefix = 0u;
-    st.n = s < 2 ? n : 0u;
-    st.valid = (s < 2 && n > 0) ? 1u : 0u;
-    st.k = s == 0 ? rank_of(0.05, n) : (s == 1 ? rank_of(0.95, n) : 0u);
+    st.n = part == 0 ? n : 0u;
+    st.valid = (part == 0 && n > 0) ? 1u : 0u;
+    st.k = part == 0 ? rank_of(sg == 0 ? 0.05 : 0.95, n) : 0u;
     sel_store(S, sg, 0, st);
     sel_store(S, sg, 1, st);
-    if (s >= 2) w.cnt[sg] = 0u;
   }
 }
 
@@ -86,16 +87,18 @@ __global__ __launch_bounds__(256) void k_q_delta(RasterArgs a, QuantWS w) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
   w.dkey[i] = f2key(voxel_footprint(a, i));
-  if (a.wmax) w.wkey[i] = f2key(a.wmax[i]);
 }
 
-// Histogram of the current digit for the selections of S.  dual: every
+
+// Histogram of the current digit for the selections of S, over keys[] or,
+// when keys is null, the order keys of vals[].  dual: every
 // element counts towards segments 0 and 1 (p5 and p95 of the same keys);
 // otherwise the element's segment is its label.  With cnt (pass 0 of the
 // per-bin selection) the initial states are the ranks ceil(q |V_b|) of the
 // bin counts.  The block counts into ncopy padded lane-indexed copies of its
 // nseg x 256 bins.
-__global__ __launch_bounds__(256) void k_q_hist(const uint32_t* keys, const uint8_t* labels, int64_t n,
+__global__ __launch_bounds__(256) void k_q_hist(const uint32_t* keys, const float* vals,
+                                                const uint8_t* labels, int64_t n,
                                                 SelSet S, int pass, int dual, int ncopy,
                                                 const uint32_t* cnt, double q) {
   extern __shared__ uint32_t lh[];
@@ -134,8 +137,11 @@ __global__ __launch_bounds__(256) void k_q_hist(const uint32_t* keys, const uint
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       const int64_t i = base + int64_t(u) * 256;
-      kk[u] = i < n ? keys[i] : 0u;
-      ss[u] = (i < n && !dual && labels) ? int(labels[i]) : 0;
+      // keys, or the order keys of float values (read directly each pass)
+      kk[u] = i < n ? (keys ? keys[i] : f2key(vals[i])) : 0u;
+      // a label past the last segment counts in the last (the histogram
+      // copies hold nseg segments)
+      ss[u] = (i < n && !dual && labels) ? min(int(labels[i]), nseg - 1) : 0;
     }
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
@@ -207,7 +213,7 @@ __global__ __launch_bounds__(256) void k_q_prune(int64_t n, int B, QuantWS w, co
   __syncthreads();
   if (blockIdx.x == 0 && threadIdx.x < B) tau[threadIdx.x] = s_tau[threadIdx.x];
   for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256)
-    prune[i] = wmax[i] <= s_tau[w.bins[i]] ? 1u : 0u;
+    prune[i] = wmax[i] <= s_tau[min(int(w.bins[i]), B - 1)] ? 1u : 0u;
 }
 
 // histogram copies: as many as fit in 64 KB of LDS, at most 16
@@ -228,24 +234,32 @@ static uint32_t grid_for(int64_t n) {
   return uint32_t(b);
 }
 
-hipError_t run_depth_quantile(const RasterArgs& a, int B, double q, void* ws, float* tau,
-                              uint8_t* prune, uint8_t* out_bins, hipStream_t s) {
+hipError_t run_depth_bins(const RasterArgs& a, int B, void* ws, uint8_t* out_bins, hipStream_t s) {
   QuantWS w = quant_bind(ws, a.n, B);
-  const uint32_t n32 = uint32_t(a.n);
-  hipLaunchKernelGGL(k_q_setup, dim3(2 + B), dim3(256), 0, s, w, B, n32);
+  hipLaunchKernelGGL(k_q_setup, dim3(2), dim3(256), 0, s, w, B, uint32_t(a.n), 0);
   if (a.n > 0) {
     hipLaunchKernelGGL(k_q_delta, dim3(uint32_t((a.n + 255) / 256)), dim3(256), 0, s, a, w);
     const uint32_t g = grid_for(a.n);
     // p5 and p95 of delta: segments 0 and 1 over every voxel, in the same passes
     for (int pass = 0; pass < 4; ++pass)
       hipLaunchKernelGGL(k_q_hist, dim3(g), dim3(256), hist_lds(2, kCopiesDual), s,
-                         (const uint32_t*)w.dkey, (const uint8_t*)nullptr, a.n, w.pct, pass, 1,
-                         kCopiesDual, (const uint32_t*)nullptr, q);
+                         (const uint32_t*)w.dkey, (const float*)nullptr, (const uint8_t*)nullptr,
+                         a.n, w.pct, pass, 1, kCopiesDual, (const uint32_t*)nullptr, 0.5);
     hipLaunchKernelGGL(k_q_bins, dim3(g), dim3(256), B * 4, s, a.n, B, w, out_bins);
+  }
+  return hipGetLastError();
+}
+
+hipError_t run_depth_cutoff(const RasterArgs& a, int B, double q, void* ws, float* tau,
+                            uint8_t* prune, hipStream_t s) {
+  QuantWS w = quant_bind(ws, a.n, B);
+  hipLaunchKernelGGL(k_q_setup, dim3(B), dim3(256), 0, s, w, B, uint32_t(a.n), 1);
+  if (a.n > 0) {
+    const uint32_t g = grid_for(a.n);
     const int cb = binned_copies(B);
     for (int pass = 0; pass < 4; ++pass)
-      hipLaunchKernelGGL(k_q_hist, dim3(g), dim3(256), hist_lds(B, cb), s, (const uint32_t*)w.wkey,
-                         (const uint8_t*)w.bins, a.n, w.bin, pass, 0, cb,
+      hipLaunchKernelGGL(k_q_hist, dim3(g), dim3(256), hist_lds(B, cb), s, (const uint32_t*)nullptr,
+                         (const float*)a.wmax, (const uint8_t*)w.bins, a.n, w.bin, pass, 0, cb,
                          pass == 0 ? (const uint32_t*)w.cnt : (const uint32_t*)nullptr, q);
   }
   hipLaunchKernelGGL(k_q_prune, dim3(grid_for(a.n)), dim3(256), 0, s, a.n, B, w, a.wmax, tau, prune);
@@ -266,16 +280,14 @@ uint64_t range_ws_bytes(int64_t n) { return quant_ws_bytes(n, 1); }
 
 hipError_t run_footprint_range(const RasterArgs& a, void* ws, float* range, hipStream_t s) {
   QuantWS w = quant_bind(ws, a.n, 1);
-  RasterArgs b = a;
-  b.wmax = nullptr;
-  hipLaunchKernelGGL(k_q_setup, dim3(3), dim3(256), 0, s, w, 1, uint32_t(a.n));
+  hipLaunchKernelGGL(k_q_setup, dim3(2), dim3(256), 0, s, w, 1, uint32_t(a.n), 0);
   if (a.n > 0) {
-    hipLaunchKernelGGL(k_q_delta, dim3(uint32_t((a.n + 255) / 256)), dim3(256), 0, s, b, w);
+    hipLaunchKernelGGL(k_q_delta, dim3(uint32_t((a.n + 255) / 256)), dim3(256), 0, s, a, w);
     const uint32_t g = grid_for(a.n);
     for (int pass = 0; pass < 4; ++pass)
       hipLaunchKernelGGL(k_q_hist, dim3(g), dim3(256), hist_lds(2, kCopiesDual), s,
-                         (const uint32_t*)w.dkey, (const uint8_t*)nullptr, a.n, w.pct, pass, 1,
-                         kCopiesDual, (const uint32_t*)nullptr, 0.5);
+                         (const uint32_t*)w.dkey, (const float*)nullptr, (const uint8_t*)nullptr,
+                         a.n, w.pct, pass, 1, kCopiesDual, (const uint32_t*)nullptr, 0.5);
   }
   hipLaunchKernelGGL(k_q_range, dim3(1), dim3(128), 0, s, w, range);
   return hipGetLastError();

@@ -21,8 +21,9 @@ hipError_t run_lf_weight(const lv_camera* cams_dev, const lv_camera* cams_host, 
 hipError_t run_l1_grad(const lv_camera* cams_dev, int V, uint64_t max_pix, const float* rgb,
                        const float* target, const float* weight, float* loss, float* d_rgb,
                        hipStream_t s);
-hipError_t run_depth_quantile(const RasterArgs& a, int B, double q, void* ws, float* tau,
-                              uint8_t* prune, uint8_t* out_bins, hipStream_t s);
+hipError_t run_depth_bins(const RasterArgs& a, int B, void* ws, uint8_t* out_bins, hipStream_t s);
+hipError_t run_depth_cutoff(const RasterArgs& a, int B, double q, void* ws, float* tau,
+                            uint8_t* prune, hipStream_t s);
 uint64_t guard_ws_bytes(int64_t n);
 uint64_t split_ws_bytes(int64_t n);
 hipError_t run_footprint_range(const RasterArgs& a, void* ws, float* range, hipStream_t s);
@@ -460,6 +461,36 @@ uint64_t lv_quantile_workspace_size(int64_t n, int32_t n_bins) {
   return lv::quant_ws_bytes(n, n_bins);
 }
 
+lv_status lv_depth_bins(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
+                        int32_t n_bins, void* workspace, uint8_t* bins, hipStream_t stream) {
+  if (!ctx) return LV_ERR_ARG;
+  lv_status s = check_voxels(ctx, vox, false);
+  if (s != LV_OK) return s;
+  if ((s = check_frame(ctx, frame)) != LV_OK) return s;
+  if (n_bins < 1 || n_bins > 64) return fail(ctx, LV_ERR_ARG, "n_bins must be in [1, 64]");
+  if (!workspace) return fail(ctx, LV_ERR_ARG, "workspace must be non-NULL");
+  lv::Layout L;
+  lv::RasterArgs a = make_args(L, workspace, vox, frame, nullptr);
+  LV_TRY(lv::run_depth_bins(a, n_bins, workspace, bins, stream), "depth_bins");
+  return LV_OK;
+}
+
+lv_status lv_depth_cutoff(lv_context* ctx, const lv_voxels* vox, const float* wmax, int32_t n_bins,
+                          double q, void* workspace, float* tau, uint8_t* prune, hipStream_t stream) {
+  if (!ctx) return LV_ERR_ARG;
+  lv_status s = check_voxels(ctx, vox, false);
+  if (s != LV_OK) return s;
+  if (n_bins < 1 || n_bins > 64) return fail(ctx, LV_ERR_ARG, "n_bins must be in [1, 64]");
+  if (!(q > 0.0 && q <= 1.0)) return fail(ctx, LV_ERR_ARG, "q must be in (0, 1]");
+  if (!workspace || !tau || (vox->n > 0 && (!wmax || !prune)))
+    return fail(ctx, LV_ERR_ARG, "workspace/tau/wmax/prune must be non-NULL");
+  lv::Layout L;
+  lv::RasterArgs a = make_args(L, workspace, vox, nullptr, nullptr);
+  a.wmax = const_cast<float*>(wmax);
+  LV_TRY(lv::run_depth_cutoff(a, n_bins, q, workspace, tau, prune, stream), "depth_cutoff");
+  return LV_OK;
+}
+
 lv_status lv_depth_quantile(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
                             const float* wmax, int32_t n_bins, double q, void* workspace,
                             float* tau, uint8_t* prune, uint8_t* bins, hipStream_t stream) {
@@ -471,11 +502,8 @@ lv_status lv_depth_quantile(lv_context* ctx, const lv_voxels* vox, const lv_fram
   if (!(q > 0.0 && q <= 1.0)) return fail(ctx, LV_ERR_ARG, "q must be in (0, 1]");
   if (!workspace || !tau || (vox->n > 0 && (!wmax || !prune)))
     return fail(ctx, LV_ERR_ARG, "workspace/tau/wmax/prune must be non-NULL");
-  lv::Layout L;
-  lv::RasterArgs a = make_args(L, workspace, vox, frame, nullptr);
-  a.wmax = const_cast<float*>(wmax);
-  LV_TRY(lv::run_depth_quantile(a, n_bins, q, workspace, tau, prune, bins, stream), "depth_quantile");
-  return LV_OK;
+  if ((s = lv_depth_bins(ctx, vox, frame, n_bins, workspace, bins, stream)) != LV_OK) return s;
+  return lv_depth_cutoff(ctx, vox, wmax, n_bins, q, workspace, tau, prune, stream);
 }
 
 void lv_default_guard(lv_guard_params* p) {

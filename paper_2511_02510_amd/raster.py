@@ -266,6 +266,21 @@ def depth_quantile(ctx, vox, frame, wmax, n_bins, q, workspace, tau, prune, bins
                                         _p(prune), _p(bins), _stream(stream)), "lv_depth_quantile")
 
 
+def depth_bins(ctx, vox, frame, n_bins, workspace, bins=None, stream=None):
+    """The w_max-independent half of depth_quantile (delta, p5/p95, bins) into
+    workspace; depth_cutoff finishes it once w_max is known."""
+    ctx.check(ctx.lib.lv_depth_bins(ctx.h, ctypes.byref(vox.struct), ctypes.byref(frame.struct),
+                                    int(n_bins), _p(workspace), _p(bins), _stream(stream)),
+              "lv_depth_bins")
+
+
+def depth_cutoff(ctx, vox, wmax, n_bins, q, workspace, tau, prune, stream=None):
+    """tau and prune from w_max on a workspace filled by depth_bins."""
+    ctx.check(ctx.lib.lv_depth_cutoff(ctx.h, ctypes.byref(vox.struct), _p(wmax), int(n_bins),
+                                      float(q), _p(workspace), _p(tau), _p(prune), _stream(stream)),
+              "lv_depth_cutoff")
+
+
 def guard_params(**kw):
     """lv_guard_params with the library defaults, overridden by keyword
     (alpha, m_low, m_high, rho, w_keep, cap_frac)."""

@@ -104,6 +104,41 @@ def test_depth_quantile_bit_exact_on_same_wmax(ctx):
     assert np.all((prune.cpu().numpy() == ref2["prune"]) | near)
 
 
+def test_depth_bins_then_cutoff_twice(ctx):
+    # the split form: the binning once (before any w_max exists), then the
+    # cutoff for two different w_max on the same workspace; each result
+    # bit-identical to the oracle's quantile of that w_max, and the bins to
+    # its bins
+    import paper_2511_02510_amd as lv
+    import torch
+    scene = small_shell(30000, seed=24, lmin=5, lmax=9, clutter=0.1)
+    cams = synth.make_cameras_ring(np.random.default_rng(2), 3)
+    cams = [look_at(c.o, c.width // 8, c.height // 8) for c in cams]
+    say("depth binning then cutoff twice, 30k voxels, 3 views")
+    vox = lv.Voxels.from_scene(scene, ctx.device)
+    frame = lv.Frame(cams, ctx.device)
+    nb = 12
+    ws = torch.empty(lv.quantile_workspace_size(vox.n, nb), dtype=torch.uint8, device=ctx.device)
+    ws.fill_(0xA5)   # stale contents must not matter
+    tau = torch.empty(nb, device=ctx.device)
+    prune = torch.empty(vox.n, dtype=torch.uint8, device=ctx.device)
+    bins = torch.empty(vox.n, dtype=torch.uint8, device=ctx.device)
+    lv.depth_bins(ctx, vox, frame, nb, ws, bins)
+    rng = np.random.default_rng(25)
+    for q, wm in [(0.1, rng.random(scene.n).astype(np.float32)),
+                  (0.3, np.round(rng.random(scene.n) * 8).astype(np.float32) / 8)]:
+        lv.depth_cutoff(ctx, vox, to_dev(wm, ctx.device), nb, q, ws, tau, prune)
+        torch.cuda.synchronize()
+        ref = oquant.depth_quantile(scene, cams, wm, nb, q)
+        assert np.array_equal(bins.cpu().numpy(), ref["bins"])
+        assert np.array_equal(tau.cpu().numpy(), ref["tau"])
+        assert np.array_equal(prune.cpu().numpy(), ref["prune"])
+    with pytest.raises(lv.LiteVoxelError):
+        lv.depth_bins(ctx, vox, frame, 65, ws)
+    with pytest.raises(lv.LiteVoxelError):
+        lv.depth_cutoff(ctx, vox, to_dev(wm, ctx.device), nb, 0.0, ws, tau, prune)
+
+
 def test_depth_quantile_degenerate_inputs(ctx):
     import paper_2511_02510_amd as lv
     import torch
