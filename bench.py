@@ -329,8 +329,9 @@ def main():
     phases = {k: (ms / max(c, 1)) for k, (ms, c) in ph.items()}
     log("[bench] phase ms/launch: " + ", ".join(f"{k} {v:.3f}" for k, v in phases.items()))
 
-    # ---- graph capture of one whole step (loss weight and depth quantile on
-    # a second stream beside the forward and the L1 gradient)
+    # ---- graph capture of one whole step (loss weight and the depth
+    # quantile's binning beside the forward, its cutoff beside the L1
+    # gradient, on a second stream)
     lv.graph_begin(ctx, stream)
     step(overlap=True)
     lv.graph_end(ctx, stream)

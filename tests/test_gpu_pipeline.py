@@ -303,10 +303,11 @@ def test_graph_replays_match_eager(ctx):
 
 
 def test_two_stream_graph_matches_eager(ctx):
-    """The loss weight on a second stream beside the forward and the depth
-    quantile beside the backward, joined by events and captured in one graph:
-    every replay (with eager work between them) equals the one-stream eager
-    step."""
+    """The step as the benchmark arranges it: the loss weight and the depth
+    quantile's binning on a second stream beside the forward, the quantile's
+    cutoff beside the L1 gradient, joined by events and captured in one
+    graph: every replay (with eager work between them) equals the one-stream
+    eager step, which runs the whole quantile in one call."""
     import paper_2511_02510_amd as lv
     import torch
     scene = small_shell(20000, seed=29, lmin=5, lmax=9, clutter=0.1)
@@ -342,17 +343,18 @@ def test_two_stream_graph_matches_eager(ctx):
         if overlap:
             e_w = torch.cuda.Event()
             e_w.record(side)
+            lv.depth_bins(ctx, vox, frame, 16, qws, stream=side)   # needs no w_max
         r.forward(rgb, depth, alpha, wmax, stream=stream, verify=False)
         if overlap:
             e_f = torch.cuda.Event()
             e_f.record(stream)
             stream.wait_event(e_w)
-        if overlap:
             side.wait_event(e_f)
-        lv.depth_quantile(ctx, vox, frame, wmax, 16, 0.1, qws, tau, prune, stream=aux)
-        if overlap:
+            lv.depth_cutoff(ctx, vox, wmax, 16, 0.1, qws, tau, prune, stream=side)
             e_q = torch.cuda.Event()
             e_q.record(side)
+        else:
+            lv.depth_quantile(ctx, vox, frame, wmax, 16, 0.1, qws, tau, prune, stream=stream)
         lv.l1_grad(ctx, frame, rgb, tgt, weight, loss, d_rgb, stream=stream)
         if overlap:
             stream.wait_event(e_q)
