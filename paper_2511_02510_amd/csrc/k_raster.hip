@@ -227,10 +227,10 @@ __device__ __forceinline__ float opacity(float tau, float ex) {
 __device__ __forceinline__ int pix_x_of_lane(int lane) { return ((lane >> 4) & 1) * 4 + (lane & 3); }
 __device__ __forceinline__ int pix_y_of_lane(int lane) { return (lane >> 5) * 4 + ((lane >> 2) & 3); }
 
-// One step of the scan over 11 values: v += (lane - K of the same row) * f,
-// with f = 1 where that lane lies in this lane's run and 0 elsewhere, as one
-// fused multiply-add per value that reads the shifted operand through DPP
-// (lanes with no source in the row keep v).  The leading and trailing s_nop
+// One step of the scan over 11 values: v += v' * f, where v' is the value
+// of lane - K in the same 16-lane row and f = 1 when that lane lies in this
+// lane's run, 0 otherwise; one fused multiply-add per value that reads v'
+// through DPP (a lane with no source in its row keeps v).  The leading and trailing s_nop
 // give the two wait states a DPP read needs after a VALU write of its
 // operand, on both sides of the block.  Every lane of the wave must be active.
 #define LV_SEG_FMAC(K, R) "v_fmac_f32_dpp %" #R ", %" #R ", %11 row_shr:" #K " row_mask:0xf bank_mask:0xf\n"
