@@ -597,10 +597,33 @@ hipError_t launch_order(const RasterArgs& a, hipStream_t s) {
 // until one run remains.  Keys are unique for non-overlapping leaves, so the
 // order is deterministic.
 
+__device__ __forceinline__ void cmp_swap(unsigned long long& x, unsigned long long& y, bool asc) {
+  if ((x > y) == asc) {
+    const unsigned long long t = x;
+    x = y;
+    y = t;
+  }
+}
+
+// Bitonic network over npow (a power of two) keys in LDS.  Stages whose
+// pairs lie more than 2 apart go through LDS, one pair per thread and a
+// barrier each; the last two stages of every merge (distances 2 and 1) stay
+// inside aligned quads and run in registers, one quad per thread.  The
+// network and its order of stages are the plain bitonic sort's.
 template <int NT>
 __device__ void lds_bitonic(unsigned long long* sk, uint32_t npow) {
+  if (npow < 4) {   // one pair at most
+    if (npow == 2 && threadIdx.x == 0) {
+      unsigned long long x = sk[0], y = sk[1];
+      cmp_swap(x, y, true);
+      sk[0] = x;
+      sk[1] = y;
+    }
+    __syncthreads();
+    return;
+  }
   for (uint32_t k = 2; k <= npow; k <<= 1) {
-    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+    for (uint32_t j = k >> 1; j > 2; j >>= 1) {
       for (uint32_t i = threadIdx.x; i < (npow >> 1); i += NT) {
         const uint32_t lo = ((i & ~(j - 1)) << 1) | (i & (j - 1));
         const uint32_t hi = lo + j;
@@ -610,6 +633,25 @@ __device__ void lds_bitonic(unsigned long long* sk, uint32_t npow) {
       }
       __syncthreads();
     }
+    for (uint32_t qd = threadIdx.x; qd < (npow >> 2); qd += NT) {
+      const uint32_t b = qd << 2;
+      unsigned long long x0 = sk[b], x1 = sk[b + 1], x2 = sk[b + 2], x3 = sk[b + 3];
+      if (k == 2) {   // pairs (b, b+1) ascending, (b+2, b+3) descending
+        cmp_swap(x0, x1, true);
+        cmp_swap(x2, x3, false);
+      } else {        // one direction for the whole quad
+        const bool asc = (b & k) == 0;
+        cmp_swap(x0, x2, asc);
+        cmp_swap(x1, x3, asc);
+        cmp_swap(x0, x1, asc);
+        cmp_swap(x2, x3, asc);
+      }
+      sk[b] = x0;
+      sk[b + 1] = x1;
+      sk[b + 2] = x2;
+      sk[b + 3] = x3;
+    }
+    __syncthreads();
   }
 }
 
