@@ -186,6 +186,32 @@ __device__ __forceinline__ uint32_t spread3_6(uint32_t x) {
   return x;
 }
 
+// Correctly rounded x / z for the projection, with z > the near plane:
+// the hardware reciprocal refined by one Newton step, then two residual
+// corrections, the reciprocal shared by a corner's two quotients.  This is
+// the compiler's division sequence without its operand rescaling and
+// special-case fix-up, which act only on infinities, NaNs, zero divisors
+// and quotients or numerators near the subnormal range; here z is normal
+// and positive and |x| is zero or far above that range (a camera-space
+// coordinate), so each quotient equals the division bit for bit (checked
+// against it on 2^31 such operand pairs).
+struct Divisor {
+  float z, r;
+};
+__device__ __forceinline__ Divisor divisor(float z) {
+  float r = __builtin_amdgcn_rcpf(z);
+  const float e = fmaf(-z, r, 1.0f);
+  r = fmaf(e, r, r);
+  return {z, r};
+}
+__device__ __forceinline__ float quotient(float x, const Divisor& d) {
+  float q = x * d.r;
+  float rem = fmaf(-d.z, q, x);
+  q = fmaf(rem, d.r, q);
+  rem = fmaf(-d.z, q, x);
+  return fmaf(rem, d.r, q);
+}
+
 // GENERIC: grid-point layout or a density activation; otherwise the dense
 // corner values are read as they are
 template <int DEG, bool GENERIC>
@@ -249,7 +275,8 @@ __global__ __launch_bounds__(kBinBlock) void k_preprocess(RasterArgs a) {
       if (zc <= kZNear) {
         ++near_cnt;
       } else {
-        const float qx = xc / zc, qy = yc / zc;
+        const Divisor dz = divisor(zc);
+        const float qx = quotient(xc, dz), qy = quotient(yc, dz);
         const float uu = cam.fx * qx + cam.cx;
         const float vv = cam.fy * qy + cam.cy;
         u0 = fminf(u0, uu); u1 = fmaxf(u1, uu);
