@@ -402,3 +402,108 @@ def test_gamma_schedule_eq9():
     # continuous at both knots
     for t in (0.3 * T, 0.6 * T):
         assert abs(loss.gamma_schedule(t - 1e-6, T) - loss.gamma_schedule(t, T)) < 1e-6
+
+
+# ------------------------------------------- depth proxy by hand (R16)
+def _camera_facing(centre, forward, dist, fx, fy, width=64, height=48, roll=0.0):
+    """A pinhole camera whose optical axis passes through `centre` at depth
+    `dist` along the unit `forward` direction; rows of R are right, down,
+    forward (turned by `roll` about the axis), so R is not axis-aligned."""
+    f = np.asarray(forward, np.float64)
+    f /= np.linalg.norm(f)
+    r = np.cross(f, [0.0, 1.0, 0.0])
+    r /= np.linalg.norm(r)
+    d = np.cross(f, r)
+    cr, sr = math.cos(roll), math.sin(roll)
+    r, d = cr * r + sr * d, -sr * r + cr * d
+    o = np.asarray(centre, np.float64) - dist * f
+    return Camera(R=np.stack([r, d, f]).astype(np.float32), o=o.astype(np.float32),
+                  fx=float(np.float32(fx)), fy=float(np.float32(fy)), cx=width / 2.0,
+                  cy=height / 2.0, width=width, height=height)
+
+
+def test_depth_proxy_hand_values():
+    # two level-3 leaves of the root [-1, 1]^3 (edge 1/4): centres are exact
+    ijk = np.array([[3, 5], [2, 6], [4, 1]], np.uint16)
+    sc = Scene(root_min=np.array([-1, -1, -1], np.float32), root_size=2.0, ijk=ijk,
+               level=np.array([3, 3], np.uint8), density=np.ones((8, 2), np.float32),
+               sh=np.ones((3, 2), np.float32), sh_degree=0)
+    centre = np.array([-1 + 0.25 * (3 + 0.5), -1 + 0.25 * (2 + 0.5), -1 + 0.25 * (4 + 0.5)])
+    fwd_a = np.array([0.3, -0.2, 0.9])
+    fwd_b = np.array([-0.7, 0.4, 0.2])
+    # A: on axis at depth 3.0, fx != fy; B: on axis at depth 2.0 with a larger fx
+    # (smaller spacing 2/900 < 3/700); C: the voxel lies behind it (z < 0)
+    cam_a = _camera_facing(centre, fwd_a, 3.0, fx=700.0, fy=350.0, roll=0.4)
+    cam_b = _camera_facing(centre, fwd_b, 2.0, fx=900.0, fy=1500.0, roll=-1.1)
+    cam_c = _camera_facing(centre, -fwd_a, -2.5, fx=50.0, fy=50.0)
+    delta = quantile.depth_proxy(sc, [cam_a])
+    assert abs(delta[0] - 3.0 / 700.0) < 3e-6 * (3.0 / 700.0)        # depth / fx, not fy
+    # the spacing uses the camera-space depth, not the distance: the second
+    # voxel is off the axis, and its depth is the projection on the axis
+    c2 = np.array([-1 + 0.25 * 5.5, -1 + 0.25 * 6.5, -1 + 0.25 * 1.5])
+    f = fwd_a / np.linalg.norm(fwd_a)
+    z2 = float(f @ (c2 - (centre - 3.0 * f)))
+    assert abs(delta[1] - z2 / 700.0) < 3e-6 * abs(z2 / 700.0)
+    assert abs(np.linalg.norm(c2 - (centre - 3.0 * f)) - z2) > 0.05
+    both = quantile.depth_proxy(sc, [cam_a, cam_b])
+    assert abs(both[0] - 2.0 / 900.0) < 3e-6 * (2.0 / 900.0)         # minimum over views
+    swapped = quantile.depth_proxy(sc, [cam_b, cam_a])
+    assert swapped[0] == both[0]
+    behind = quantile.depth_proxy(sc, [cam_c])
+    assert np.all(np.isinf(behind))                                   # no view in front
+    assert quantile.depth_proxy(sc, [cam_c, cam_a])[0] == delta[0]
+
+
+# ------------------------------------------ tile numbering by hand (R6)
+def test_tile_lists_global_numbering_by_hand():
+    # view 0 is 40 x 20 px (3 x 2 tiles of 16), view 1 is 20 x 40 px (2 x 3):
+    # global tile id = base(view) + ty * tiles_x(view) + tx, bases 0 and 6
+    cams = [Camera(R=np.eye(3, dtype=np.float32), o=np.zeros(3, np.float32), fx=1.0, fy=1.0,
+                   cx=0.0, cy=0.0, width=40, height=20),
+            Camera(R=np.eye(3, dtype=np.float32), o=np.zeros(3, np.float32), fx=1.0, fy=1.0,
+                   cx=0.0, cy=0.0, width=20, height=40)]
+    n = 4
+    vis = np.zeros((2, n), np.uint8)
+    rect = np.zeros((2, n, 4), np.int32)
+    code = np.zeros((2, n), np.uint64)
+    # (view, voxel): pixel-centre rect (x0, x1, y0, y1), code
+    recs = {(0, 0): ((17, 33, 0, 5), 50), (0, 1): ((20, 22, 2, 3), 7),
+            (0, 2): ((0, 39, 19, 19), 3), (1, 1): ((0, 3, 16, 35), 9),
+            (1, 3): ((19, 19, 39, 39), 1)}
+    for (v, i), (r, c) in recs.items():
+        vis[v, i] = 1
+        rect[v, i] = r
+        code[v, i] = c
+    start, ids, keys = oracle.tile_lists(cams, vis, rect, code, 16)
+    expect = {1: [1, 0], 2: [0], 3: [2], 4: [2], 5: [2], 8: [1], 10: [1], 11: [3]}
+    assert start.shape[0] == 13
+    for t in range(12):
+        got = list(ids[start[t]:start[t + 1]])
+        assert got == expect.get(t, []), (t, got)
+        tile_of_key = keys[start[t]:start[t + 1]] >> np.uint64(36)
+        assert np.all(tile_of_key == t)
+
+
+# --------------------------------------------- colour clamp by hand (R8)
+def test_negative_colour_channel_is_clamped():
+    sigma = float(np.float32(0.9))
+    col = (float(np.float32(-0.3)), float(np.float32(0.5)), float(np.float32(0.0)))
+    bg = (0.25, 0.5, 0.75)
+    sc = one_voxel_scene(sigma, col)
+    cam = axis_camera((0.0, 0.0, -3.0), (0.0, 0.0, 0.0))
+    out = oracle.render(sc, [cam], bg=bg)
+    A = out["alpha"]
+    rgb = out["views"][0].reshape(3, -1)
+    assert A.max() > 0.3
+    # the clamped channel shows only the background through T_K
+    assert np.max(np.abs(rgb[0] - (1.0 - A) * bg[0])) < 1e-14
+    assert np.max(np.abs(rgb[1] - (A * col[1] + (1.0 - A) * bg[1]))) < 1e-14
+    assert np.max(np.abs(rgb[2] - (1.0 - A) * bg[2])) < 1e-14
+    # no gradient reaches a coefficient through a clamped (or zero) channel;
+    # the open channel's constant term gets sum_p g_p w_p with w_p = A_p
+    rng = np.random.default_rng(3)
+    g = rng.normal(0.0, 1.0, 3 * A.shape[0])
+    _, dsh = oracle.backward(sc, [cam], g, bg=bg)
+    assert dsh[0, 0] == 0.0 and dsh[2, 0] == 0.0
+    gv = g.reshape(3, -1)
+    assert abs(dsh[1, 0] - float(gv[1] @ A)) < 1e-10 * max(1.0, abs(dsh[1, 0]))
