@@ -308,7 +308,7 @@ def main():
     with torch.cuda.stream(stream):
         step(verify=True, overlap=False)    # sizes the pair buffers exactly
     torch.cuda.synchronize()
-    fits, Q = lv.check_overflow(ctx, vox, frame, r.st, r.workspace, stream=stream)
+    fits, Q = lv.check_overflow(ctx, vox, frame, r.st, r.saved, stream=stream)
     assert fits
     log(f"[bench] pairs Q={Q} capacity={r.st.pair_capacity}")
 
@@ -406,7 +406,7 @@ def main():
     fwd_roof = fwd_alg / (phases["composite_fwd"] * 1e-3) / 1e9
 
     # ---- whole-forward and whole-step HBM fractions (all phases)
-    bins = lv.export_bins(ctx, vox, frame, r.st, r.workspace)
+    bins = lv.export_bins(ctx, vox, frame, r.st, r.saved)
     M = int(np.count_nonzero(bins["vis"]))
     del bins
     b_fwd, b_bwd = step_bytes(scene.n, M, Q, P, int(vox.sh.shape[0]))

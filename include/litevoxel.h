@@ -33,8 +33,12 @@
  *
  * Conventions for every call:
  *   - Device pointers point to memory of the context's device, owned by the
- *     caller; the library never frees or keeps them beyond the call, except
- *     the workspace, whose contents lv_forward leaves for lv_backward.
+ *     caller; the library never frees or keeps them beyond the call.  The
+ *     rasterizer takes two caller-owned buffers: `saved`, the state one
+ *     lv_forward leaves for the lv_backward of the same pass (tile lists,
+ *     voxel and view records, per-pixel state), and `workspace`, scratch
+ *     that every call may overwrite.  Each pass that will be differentiated
+ *     later keeps its own `saved`; one workspace serves them all.
  *   - All device work is enqueued on the given stream; no call below
  *     synchronises except lv_check_overflow, lv_export_bins, lv_autotune
  *     and lv_read_timings, which say so.  The enqueuing calls allocate no
@@ -148,24 +152,30 @@ void lv_default_settings(lv_settings* s);   /* tile 16, chunk 64, chunk_bwd 0, t
 /* Host-only argument checks (no device access): LV_OK or LV_ERR_ARG. */
 lv_status lv_validate(const lv_voxels* vox, const lv_frame* frame, const lv_settings* st);
 
-/* Host-only planning: bytes of device workspace lv_forward/lv_backward need
- * for these shapes and settings (capacity included).  ctx may be NULL. */
+/* Host-only planning: bytes of the device workspace (scratch) and of the
+ * saved state that lv_forward/lv_backward need for these shapes and
+ * settings (pair capacity included).  The saved state is
+ * 48 n + 32 n V + 8 P + 4 pair_capacity + 68 T bytes (T tiles, P pixels,
+ * V views) plus alignment.  ctx may be NULL. */
 lv_status lv_query_sizes(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
-                         const lv_settings* st, uint64_t* workspace_bytes);
+                         const lv_settings* st, uint64_t* workspace_bytes, uint64_t* saved_bytes);
 
 /* ------------------------------------------------------------------ forward
  * Sec. III, eq. 1-5.  Projects and bins every (voxel, view) record into
  * tiles, sorts each tile's list front to back, composites every pixel and
  * max-accumulates w_max.  Outputs: rgb [3P] (layout above), depth [P],
  * alpha [P] (all overwritten), wmax [n] (max-combined with its contents: the
- * caller zeroes it at the start of an adaptation window).  The workspace
- * (>= lv_query_sizes bytes, 256-byte aligned) keeps the tile lists and the
- * per-pixel state (index of the last hit and transmittance before it) for
- * lv_backward.  If the pairs exceed pair_capacity the outputs are invalid
- * and lv_check_overflow reports it. */
+ * caller zeroes it at the start of an adaptation window).  `saved`
+ * (>= saved_bytes of lv_query_sizes, 256-byte aligned, overwritten) receives
+ * what lv_backward reads: the view table, voxel and per-view records, the
+ * per-tile front-to-back voxel lists, the pair count and, per pixel, the
+ * index of the last hit and the transmittance before it (8 bytes; no
+ * per-sample state).  `workspace` (>= workspace_bytes, 256-byte aligned) is
+ * scratch.  If the pairs exceed pair_capacity the outputs are invalid and
+ * lv_check_overflow reports it. */
 lv_status lv_forward(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
-                     const lv_settings* st, void* workspace, float* rgb, float* depth,
-                     float* alpha, float* wmax, hipStream_t stream);
+                     const lv_settings* st, void* workspace, void* saved, float* rgb,
+                     float* depth, float* alpha, float* wmax, hipStream_t stream);
 
 /* ----------------------------------------------------------------- backward
  * Adjoint of eq. 2-4 (and of the trilinear opacity and SH colour models):
@@ -175,26 +185,30 @@ lv_status lv_forward(lv_context* ctx, const lv_voxels* vox, const lv_frame* fram
  * [n_grid] for grid points (each point sums the gradients of the corners
  * that read it), with respect to the stored values (through the
  * activation).  Transmittance is recomputed back to front from the state
- * lv_forward left in the workspace (same vox/frame/settings/workspace). */
+ * the forward pass left in `saved`, which is only read; vox, frame and
+ * settings (pair capacity included) must be those of that forward, and
+ * vox's parameter arrays must hold the values it rendered.  `workspace` is
+ * scratch of workspace_bytes (any buffer, not necessarily the forward's). */
 lv_status lv_backward(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
-                      const lv_settings* st, void* workspace, const float* d_rgb,
-                      const float* d_depth, const float* d_alpha, float* d_density,
-                      float* d_sh, hipStream_t stream);
+                      const lv_settings* st, void* workspace, const void* saved,
+                      const float* d_rgb, const float* d_depth, const float* d_alpha,
+                      float* d_density, float* d_sh, hipStream_t stream);
 
 /* Synchronises the stream and reports the number of (tile, voxel) pairs the
- * last lv_forward produced: LV_OK if it fitted, LV_ERR_CAPACITY otherwise. */
+ * forward pass that filled `saved` produced: LV_OK if it fitted,
+ * LV_ERR_CAPACITY otherwise. */
 lv_status lv_check_overflow(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
-                            const lv_settings* st, const void* workspace,
+                            const lv_settings* st, const void* saved,
                             uint64_t* pairs_needed, hipStream_t stream);
 
-/* Copies the binning state of the last lv_forward to host buffers
+/* Copies the binning state a forward pass left in `saved` to host buffers
  * (synchronises): tile_start [T+1] (T = total tiles, views in order,
  * row-major), ids [tile_start[T]] voxel ids in per-tile front-to-back order,
  * codes [n_views*n] 36-bit visibility codes, rects [n_views*n*4] pixel-centre
  * ranges (x0, x1, y0, y1) and vis [n_views*n] (1 = record binned).  Any
  * pointer may be NULL.  For tests and debugging. */
 lv_status lv_export_bins(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
-                         const lv_settings* st, const void* workspace, uint32_t* tile_start,
+                         const lv_settings* st, const void* saved, uint32_t* tile_start,
                          uint32_t* ids, uint64_t* codes, int32_t* rects, uint8_t* vis,
                          hipStream_t stream);
 

@@ -62,10 +62,10 @@ _SIGS = {
     "lv_default_settings": (None, [POINTER(LvSettings)]),
     "lv_validate": (c_int32, [POINTER(LvVoxels), POINTER(LvFrame), POINTER(LvSettings)]),
     "lv_query_sizes": (c_int32, [P, POINTER(LvVoxels), POINTER(LvFrame), POINTER(LvSettings),
-                                 POINTER(c_uint64)]),
-    "lv_forward": (c_int32, [P, POINTER(LvVoxels), POINTER(LvFrame), POINTER(LvSettings), P,
+                                 POINTER(c_uint64), POINTER(c_uint64)]),
+    "lv_forward": (c_int32, [P, POINTER(LvVoxels), POINTER(LvFrame), POINTER(LvSettings), P, P,
                              P, P, P, P, P]),
-    "lv_backward": (c_int32, [P, POINTER(LvVoxels), POINTER(LvFrame), POINTER(LvSettings), P,
+    "lv_backward": (c_int32, [P, POINTER(LvVoxels), POINTER(LvFrame), POINTER(LvSettings), P, P,
                               P, P, P, P, P, P]),
     "lv_check_overflow": (c_int32, [P, POINTER(LvVoxels), POINTER(LvFrame), POINTER(LvSettings),
                                     P, POINTER(c_uint64), P]),

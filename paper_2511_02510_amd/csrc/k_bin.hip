@@ -447,8 +447,8 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_top(RasterArgs a, uint32_t 
     carry += tot;
   }
   if (threadIdx.x == 0) {
-    a.ws.counters[C_PAIRS] = carry > 0xFFFFFFFFull ? 0xFFFFFFFFu : uint32_t(carry);
-    a.ws.counters[C_OVERFLOW] = carry > a.cap ? 1u : 0u;
+    a.ws.status[S_PAIRS] = carry > 0xFFFFFFFFull ? 0xFFFFFFFFu : uint32_t(carry);
+    a.ws.status[S_OVERFLOW] = carry > a.cap ? 1u : 0u;
   }
 }
 

@@ -172,11 +172,12 @@ lv_status validate_all(lv_context* ctx, const lv_voxels* vx, const lv_frame* fr,
   return LV_OK;
 }
 
-lv::RasterArgs make_args(const lv::Layout& L, void* ws, const lv_voxels* vx, const lv_frame* fr,
-                         const lv_settings* st) {
+// saved: the forward's kept state (NULL for calls that use only a workspace)
+lv::RasterArgs make_args(const lv::Layout& L, void* ws, const void* saved, const lv_voxels* vx,
+                         const lv_frame* fr, const lv_settings* st) {
   lv::RasterArgs a;
   std::memset(&a, 0, sizeof(a));
-  a.ws = lv::bind(L, ws);
+  a.ws = lv::bind(L, ws, saved ? const_cast<void*>(saved) : ws);
   a.n = vx->n;
   a.deg = vx->sh_degree;
   for (int k = 0; k < 3; ++k) a.root_min[k] = vx->root_min[k];
@@ -264,17 +265,19 @@ lv_status lv_validate(const lv_voxels* vox, const lv_frame* frame, const lv_sett
 }
 
 lv_status lv_query_sizes(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
-                         const lv_settings* st, uint64_t* workspace_bytes) {
-  if (!workspace_bytes) return fail(ctx, LV_ERR_ARG, "workspace_bytes is NULL");
+                         const lv_settings* st, uint64_t* workspace_bytes, uint64_t* saved_bytes) {
+  if (!workspace_bytes || !saved_bytes)
+    return fail(ctx, LV_ERR_ARG, "workspace_bytes/saved_bytes is NULL");
   lv::Layout L;
   lv_status s = validate_all(ctx, vox, frame, st, &L);
   if (s != LV_OK) return s;
   *workspace_bytes = L.total;
+  *saved_bytes = L.total_saved;
   return LV_OK;
 }
 
 lv_status lv_forward(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
-                     const lv_settings* st, void* workspace, float* rgb, float* depth,
+                     const lv_settings* st, void* workspace, void* saved, float* rgb, float* depth,
                      float* alpha, float* wmax, hipStream_t stream) {
   if (!ctx) return LV_ERR_ARG;
   lv::Layout L;
@@ -282,9 +285,11 @@ lv_status lv_forward(lv_context* ctx, const lv_voxels* vox, const lv_frame* fram
   if (s != LV_OK) return s;
   if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255))
     return fail(ctx, LV_ERR_ARG, "workspace must be non-NULL and 256-byte aligned");
+  if (!saved || (reinterpret_cast<uintptr_t>(saved) & 255))
+    return fail(ctx, LV_ERR_ARG, "saved must be non-NULL and 256-byte aligned");
   if (!rgb || !depth || !alpha) return fail(ctx, LV_ERR_ARG, "rgb/depth/alpha must be non-NULL");
   if (vox->n > 0 && !wmax) return fail(ctx, LV_ERR_ARG, "wmax must be non-NULL");
-  lv::RasterArgs a = make_args(L, workspace, vox, frame, st);
+  lv::RasterArgs a = make_args(L, workspace, saved, vox, frame, st);
   a.rgb = rgb;
   a.depth = depth;
   a.alpha = alpha;
@@ -321,19 +326,21 @@ lv_status lv_forward(lv_context* ctx, const lv_voxels* vox, const lv_frame* fram
 }
 
 lv_status lv_backward(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
-                      const lv_settings* st, void* workspace, const float* d_rgb,
-                      const float* d_depth, const float* d_alpha, float* d_density, float* d_sh,
-                      hipStream_t stream) {
+                      const lv_settings* st, void* workspace, const void* saved,
+                      const float* d_rgb, const float* d_depth, const float* d_alpha,
+                      float* d_density, float* d_sh, hipStream_t stream) {
   if (!ctx) return LV_ERR_ARG;
   lv::Layout L;
   lv_status s = validate_all(ctx, vox, frame, st, &L);
   if (s != LV_OK) return s;
   if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255))
     return fail(ctx, LV_ERR_ARG, "workspace must be non-NULL and 256-byte aligned");
+  if (!saved || (reinterpret_cast<uintptr_t>(saved) & 255))
+    return fail(ctx, LV_ERR_ARG, "saved must be non-NULL and 256-byte aligned");
   if (!d_rgb) return fail(ctx, LV_ERR_ARG, "d_rgb must be non-NULL");
   if (vox->n > 0 && (!d_density || !d_sh))
     return fail(ctx, LV_ERR_ARG, "d_density/d_sh must be non-NULL");
-  lv::RasterArgs a = make_args(L, workspace, vox, frame, st);
+  lv::RasterArgs a = make_args(L, workspace, saved, vox, frame, st);
   a.d_rgb = d_rgb;
   a.d_depth = d_depth;
   a.d_alpha = d_alpha;
@@ -356,36 +363,36 @@ lv_status lv_backward(lv_context* ctx, const lv_voxels* vox, const lv_frame* fra
 }
 
 lv_status lv_check_overflow(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
-                            const lv_settings* st, const void* workspace, uint64_t* pairs_needed,
+                            const lv_settings* st, const void* saved, uint64_t* pairs_needed,
                             hipStream_t stream) {
   if (!ctx) return LV_ERR_ARG;
   lv::Layout L;
   lv_status s = validate_all(ctx, vox, frame, st, &L);
   if (s != LV_OK) return s;
-  if (!workspace) return fail(ctx, LV_ERR_ARG, "workspace is NULL");
+  if (!saved) return fail(ctx, LV_ERR_ARG, "saved is NULL");
   LV_TRY(hipStreamSynchronize(stream), "synchronize");
   uint32_t c[2] = {0, 0};
-  const char* base = static_cast<const char*>(workspace) + L.off_counters;
-  LV_TRY(hipMemcpy(c, base, sizeof(c), hipMemcpyDeviceToHost), "read counters");
-  if (pairs_needed) *pairs_needed = c[lv::C_PAIRS];
-  if (c[lv::C_OVERFLOW]) {
+  const char* base = static_cast<const char*>(saved) + L.off_status;
+  LV_TRY(hipMemcpy(c, base, sizeof(c), hipMemcpyDeviceToHost), "read status");
+  if (pairs_needed) *pairs_needed = c[lv::S_PAIRS];
+  if (c[lv::S_OVERFLOW]) {
     return fail(ctx, LV_ERR_CAPACITY, "%u (tile, voxel) pairs needed, capacity %llu",
-                c[lv::C_PAIRS], (unsigned long long)L.cap);
+                c[lv::S_PAIRS], (unsigned long long)L.cap);
   }
   return LV_OK;
 }
 
 lv_status lv_export_bins(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
-                         const lv_settings* st, const void* workspace, uint32_t* tile_start,
+                         const lv_settings* st, const void* saved, uint32_t* tile_start,
                          uint32_t* ids, uint64_t* codes, int32_t* rects, uint8_t* vis,
                          hipStream_t stream) {
   if (!ctx) return LV_ERR_ARG;
   lv::Layout L;
   lv_status s = validate_all(ctx, vox, frame, st, &L);
   if (s != LV_OK) return s;
-  if (!workspace) return fail(ctx, LV_ERR_ARG, "workspace is NULL");
+  if (!saved) return fail(ctx, LV_ERR_ARG, "saved is NULL");
   LV_TRY(hipStreamSynchronize(stream), "synchronize");
-  const char* base = static_cast<const char*>(workspace);
+  const char* base = static_cast<const char*>(saved);
   std::vector<uint32_t> sub(size_t(L.T) * lv::kSpread + 1);
   LV_TRY(hipMemcpy(sub.data(), base + L.off_tstart, 4 * sub.size(), hipMemcpyDeviceToHost), "tile_start");
   std::vector<uint32_t> ts(size_t(L.T) + 1);
@@ -470,7 +477,7 @@ lv_status lv_depth_bins(lv_context* ctx, const lv_voxels* vox, const lv_frame* f
   if (n_bins < 1 || n_bins > 64) return fail(ctx, LV_ERR_ARG, "n_bins must be in [1, 64]");
   if (!workspace) return fail(ctx, LV_ERR_ARG, "workspace must be non-NULL");
   lv::Layout L;
-  lv::RasterArgs a = make_args(L, workspace, vox, frame, nullptr);
+  lv::RasterArgs a = make_args(L, workspace, nullptr, vox, frame, nullptr);
   LV_TRY(lv::run_depth_bins(a, n_bins, workspace, bins, stream), "depth_bins");
   return LV_OK;
 }
@@ -485,7 +492,7 @@ lv_status lv_depth_cutoff(lv_context* ctx, const lv_voxels* vox, const float* wm
   if (!workspace || !tau || (vox->n > 0 && (!wmax || !prune)))
     return fail(ctx, LV_ERR_ARG, "workspace/tau/wmax/prune must be non-NULL");
   lv::Layout L;
-  lv::RasterArgs a = make_args(L, workspace, vox, nullptr, nullptr);
+  lv::RasterArgs a = make_args(L, workspace, nullptr, vox, nullptr, nullptr);
   a.wmax = const_cast<float*>(wmax);
   LV_TRY(lv::run_depth_cutoff(a, n_bins, q, workspace, tau, prune, stream), "depth_cutoff");
   return LV_OK;
@@ -540,7 +547,7 @@ lv_status lv_prune_guard(lv_context* ctx, const lv_voxels* vox, const lv_frame* 
     return fail(ctx, LV_ERR_ARG, "workspace/wmax/bins/tau/ema/state/prune must be non-NULL");
   if (vox->n > int64_t(0x7FFFFFFF)) return fail(ctx, LV_ERR_ARG, "n must be below 2^31");
   lv::Layout L;
-  lv::RasterArgs a = make_args(L, workspace, vox, frame, nullptr);
+  lv::RasterArgs a = make_args(L, workspace, nullptr, vox, frame, nullptr);
   a.wmax = const_cast<float*>(wmax);
   lv::GuardParams p;
   p.alpha = g.alpha;
@@ -574,7 +581,7 @@ lv_status lv_footprint_range(lv_context* ctx, const lv_voxels* vox, const lv_fra
   if ((s = check_frame(ctx, frame)) != LV_OK) return s;
   if (!workspace || !range) return fail(ctx, LV_ERR_ARG, "workspace/range must be non-NULL");
   lv::Layout L;
-  lv::RasterArgs a = make_args(L, workspace, vox, frame, nullptr);
+  lv::RasterArgs a = make_args(L, workspace, nullptr, vox, frame, nullptr);
   LV_TRY(lv::run_footprint_range(a, workspace, range, stream), "footprint_range");
   return LV_OK;
 }
@@ -595,7 +602,7 @@ lv_status lv_subdivide_select(lv_context* ctx, const lv_voxels* vox, const lv_fr
   if (!workspace || (vox->n > 0 && (!score || !range || !split)))
     return fail(ctx, LV_ERR_ARG, "workspace/score/range/split must be non-NULL");
   lv::Layout L;
-  lv::RasterArgs a = make_args(L, workspace, vox, frame, nullptr);
+  lv::RasterArgs a = make_args(L, workspace, nullptr, vox, frame, nullptr);
   lv::SplitParams p;
   p.kappa = params->kappa;
   p.beta = params->beta;
@@ -618,7 +625,7 @@ lv_status lv_subdivide_apply(lv_context* ctx, const lv_voxels* vox, const uint8_
   if (!workspace || (vox->n > 0 && (!split || !ijk || !level || !density || !sh)))
     return fail(ctx, LV_ERR_ARG, "workspace/split/ijk/level/density/sh must be non-NULL");
   lv::Layout L;
-  lv::RasterArgs a = make_args(L, workspace, vox, nullptr, nullptr);
+  lv::RasterArgs a = make_args(L, workspace, nullptr, vox, nullptr, nullptr);
   LV_TRY(lv::run_split_apply(a, split, n_out, workspace, ijk, level, density, sh, n_needed, stream),
          "subdivide_apply");
   return LV_OK;
@@ -706,14 +713,15 @@ lv_status lv_autotune(lv_context* ctx, const lv_voxels* vox, const lv_frame* fra
   float *rgb = nullptr, *depth = nullptr, *alpha = nullptr, *wmax = nullptr, *drgb = nullptr,
         *dd = nullptr, *dsh = nullptr;
   void* ws = nullptr;
-  size_t ws_bytes = 0;
+  void* sv = nullptr;
+  size_t ws_bytes = 0, sv_bytes = 0;
   hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
   lv_status result = LV_OK;
   float best_ms = -1.0f;
   auto cleanup = [&]() {
     for (void* p : {static_cast<void*>(rgb), static_cast<void*>(depth), static_cast<void*>(alpha),
                     static_cast<void*>(wmax), static_cast<void*>(drgb), static_cast<void*>(dd),
-                    static_cast<void*>(dsh), ws})
+                    static_cast<void*>(dsh), ws, sv})
       if (p) (void)hipFree(p);
     for (hipEvent_t e : {e0, e1, e2})
       if (e) (void)hipEventDestroy(e);
@@ -750,8 +758,14 @@ lv_status lv_autotune(lv_context* ctx, const lv_voxels* vox, const lv_frame* fra
         if (hipMalloc(&ws, L.total) != hipSuccess) { result = fail(ctx, LV_ERR_HIP, "autotune: workspace"); break; }
         ws_bytes = L.total;
       }
-      if ((s = lv_forward(ctx, vox, frame, &st, ws, rgb, depth, alpha, wmax, stream)) != LV_OK) { result = s; break; }
-      s = lv_check_overflow(ctx, vox, frame, &st, ws, &needed, stream);
+      if (L.total_saved > sv_bytes) {
+        if (sv) (void)hipFree(sv);
+        sv = nullptr;
+        if (hipMalloc(&sv, L.total_saved) != hipSuccess) { result = fail(ctx, LV_ERR_HIP, "autotune: saved state"); break; }
+        sv_bytes = L.total_saved;
+      }
+      if ((s = lv_forward(ctx, vox, frame, &st, ws, sv, rgb, depth, alpha, wmax, stream)) != LV_OK) { result = s; break; }
+      s = lv_check_overflow(ctx, vox, frame, &st, sv, &needed, stream);
       if (s == LV_OK) break;
       if (s != LV_ERR_CAPACITY) { result = s; break; }
       cap = std::min<uint64_t>(needed + needed / 16 + 1024, 0xFFFFFFFFull);
@@ -764,14 +778,14 @@ lv_status lv_autotune(lv_context* ctx, const lv_voxels* vox, const lv_frame* fra
       st.chunk = chunks[ci];
       st.chunk_bwd = chunks[ci];
       float mf = 0.0f, mb = 0.0f;
-      bool run_ok = lv_forward(ctx, vox, frame, &st, ws, rgb, depth, alpha, wmax, stream) == LV_OK &&
-                    lv_backward(ctx, vox, frame, &st, ws, drgb, nullptr, nullptr, dd, dsh, stream) == LV_OK &&
+      bool run_ok = lv_forward(ctx, vox, frame, &st, ws, sv, rgb, depth, alpha, wmax, stream) == LV_OK &&
+                    lv_backward(ctx, vox, frame, &st, ws, sv, drgb, nullptr, nullptr, dd, dsh, stream) == LV_OK &&
                     hipEventRecord(e0, stream) == hipSuccess;
       for (int r = 0; r < reps && run_ok; ++r)
-        run_ok = lv_forward(ctx, vox, frame, &st, ws, rgb, depth, alpha, wmax, stream) == LV_OK;
+        run_ok = lv_forward(ctx, vox, frame, &st, ws, sv, rgb, depth, alpha, wmax, stream) == LV_OK;
       run_ok = run_ok && hipEventRecord(e1, stream) == hipSuccess;
       for (int r = 0; r < reps && run_ok; ++r)
-        run_ok = lv_backward(ctx, vox, frame, &st, ws, drgb, nullptr, nullptr, dd, dsh, stream) == LV_OK;
+        run_ok = lv_backward(ctx, vox, frame, &st, ws, sv, drgb, nullptr, nullptr, dd, dsh, stream) == LV_OK;
       run_ok = run_ok && hipEventRecord(e2, stream) == hipSuccess && hipEventSynchronize(e2) == hipSuccess &&
                hipEventElapsedTime(&mf, e0, e1) == hipSuccess && hipEventElapsedTime(&mb, e1, e2) == hipSuccess;
       fwd_ms[ci] = run_ok ? mf / reps : -1.0f;

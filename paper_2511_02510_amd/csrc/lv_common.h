@@ -60,10 +60,15 @@ struct Rec {
   uint32_t code_hi;
 };
 
-// counters block (uint32 words)
+// status words kept with the forward's saved state
+enum Status : int {
+  S_PAIRS = 0,       // number of (tile, voxel) pairs (saturating below 2^32)
+  S_OVERFLOW = 1,    // 1 if pairs > capacity
+  S_WORDS = 64
+};
+
+// counters block of the workspace (uint32 words)
 enum Counter : int {
-  C_PAIRS = 0,       // number of (tile, voxel) pairs (saturating below 2^32)
-  C_OVERFLOW = 1,    // 1 if pairs > capacity
   C_BUCKET = 8,      // [32] tile counts per length bucket
   C_BSTART = 40,     // [33] bucket starts
   C_BFILL = 80,      // [32] bucket cursors
@@ -71,7 +76,13 @@ enum Counter : int {
   C_QBWD = 128 + kQueues * kQueueStride,   // [kQueues] backward queue heads
 };
 
-// Workspace layout, computed identically on the host for sizing and launch.
+// Buffer layouts, computed identically on the host for sizing and launch.
+// Two caller-owned buffers: `saved` holds everything lv_forward leaves for
+// lv_backward (view table, voxel and view records, tile starts, tile order,
+// per-tile voxel lists, per-pixel state, pair status), so each forward pass
+// can keep its own; `workspace` is scratch that any call may overwrite
+// (counters, tile counts and cursors, the pair keys and their merge buffer,
+// the backward's gradient accumulators).
 struct Layout {
   int64_t n = 0;
   int V = 0;
@@ -82,9 +93,13 @@ struct Layout {
   uint64_t P = 0;          // total pixels
   uint64_t cap = 0;        // pair capacity
   uint32_t nblk_scan = 0;  // blocks of the tile scan
-  size_t off_views = 0, off_counters = 0, off_vox = 0, off_rec = 0, off_tcount = 0,
-         off_tstart = 0, off_tfill = 0, off_torder = 0, off_bsum = 0, off_pairs = 0,
-         off_ids = 0, off_mtmp = 0, off_nlast = 0, off_tpre = 0, off_dcol = 0, off_dden = 0;
+  // saved
+  size_t off_views = 0, off_status = 0, off_vox = 0, off_rec = 0, off_tstart = 0, off_torder = 0,
+         off_ids = 0, off_nlast = 0, off_tpre = 0;
+  size_t total_saved = 0;
+  // workspace
+  size_t off_counters = 0, off_tcount = 0, off_tfill = 0, off_bsum = 0, off_dcol = 0, off_dden = 0,
+         off_pairs = 0, off_mtmp = 0;
   size_t total = 0;
 };
 
@@ -115,64 +130,72 @@ inline bool make_layout(const lv_voxels* vox, const lv_frame* fr, const lv_setti
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
   L.off_views = take(sizeof(ViewTab) * size_t(L.V));
-  L.off_counters = take(4 * kCounterWords);
+  L.off_status = take(4 * S_WORDS);
   L.off_vox = take(sizeof(VoxRec) * size_t(L.n));
   L.off_rec = take(sizeof(Rec) * size_t(L.n) * size_t(L.V));
-  L.off_tcount = take(4 * (size_t(L.T) * kSpread + 1));
   L.off_tstart = take(4 * (size_t(L.T) * kSpread + 1));
-  L.off_tfill = take(4 * (size_t(L.T) * kSpread + 1));
   L.off_torder = take(4 * size_t(L.T + 1));
-  L.off_bsum = take(8 * size_t(L.nblk_scan + 1));   // 64-bit block sums
-  L.off_pairs = take(8 * size_t(L.cap));
-  L.off_ids = take(4 * size_t(L.cap));
-  L.off_mtmp = take(8 * size_t(L.cap));
   L.off_nlast = take(4 * size_t(L.P));
   L.off_tpre = take(4 * size_t(L.P));
+  L.off_ids = take(4 * size_t(L.cap));
+  L.total_saved = o;
+  o = 0;
+  L.off_counters = take(4 * kCounterWords);
+  L.off_tcount = take(4 * (size_t(L.T) * kSpread + 1));
+  L.off_tfill = take(4 * (size_t(L.T) * kSpread + 1));
+  L.off_bsum = take(8 * size_t(L.nblk_scan + 1));   // 64-bit block sums
   L.off_dcol = take(12 * size_t(L.n) * size_t(L.V));
   L.off_dden = take(32 * size_t(L.n));
+  L.off_pairs = take(8 * size_t(L.cap));
+  L.off_mtmp = take(8 * size_t(L.cap));
   L.total = o;
   return true;
 }
 
-// device pointers into one workspace
+// device pointers into the two buffers
 struct WS {
+  // saved
   ViewTab* views;
-  uint32_t* counters;
+  uint32_t* status;
   VoxRec* vox;
   Rec* rec;
-  uint32_t* tcount;
   uint32_t* tstart;
-  uint32_t* tfill;
   uint32_t* torder;
-  uint32_t* bsum;   // holds nblk_scan + 1 64-bit block sums
-  unsigned long long* pairs;
   uint32_t* ids;
-  unsigned long long* mtmp;
   uint32_t* nlast;
   float* tpre;
+  // workspace
+  uint32_t* counters;
+  uint32_t* tcount;
+  uint32_t* tfill;
+  uint32_t* bsum;   // holds nblk_scan + 1 64-bit block sums
   float* dcol;   // [V][n][3] colour gradient per (view, voxel)
   float* dden;   // [n][8] corner-density gradient, voxel-major
+  unsigned long long* pairs;
+  unsigned long long* mtmp;
 };
 
-inline WS bind(const Layout& L, void* base) {
-  char* b = static_cast<char*>(base);
+inline WS bind(const Layout& L, void* ws_base, void* saved_base) {
+  char* b = static_cast<char*>(saved_base);
   WS w;
   w.views = reinterpret_cast<ViewTab*>(b + L.off_views);
-  w.counters = reinterpret_cast<uint32_t*>(b + L.off_counters);
+  w.status = reinterpret_cast<uint32_t*>(b + L.off_status);
   w.vox = reinterpret_cast<VoxRec*>(b + L.off_vox);
   w.rec = reinterpret_cast<Rec*>(b + L.off_rec);
-  w.tcount = reinterpret_cast<uint32_t*>(b + L.off_tcount);
   w.tstart = reinterpret_cast<uint32_t*>(b + L.off_tstart);
-  w.tfill = reinterpret_cast<uint32_t*>(b + L.off_tfill);
   w.torder = reinterpret_cast<uint32_t*>(b + L.off_torder);
-  w.bsum = reinterpret_cast<uint32_t*>(b + L.off_bsum);
-  w.pairs = reinterpret_cast<unsigned long long*>(b + L.off_pairs);
   w.ids = reinterpret_cast<uint32_t*>(b + L.off_ids);
-  w.mtmp = reinterpret_cast<unsigned long long*>(b + L.off_mtmp);
   w.nlast = reinterpret_cast<uint32_t*>(b + L.off_nlast);
   w.tpre = reinterpret_cast<float*>(b + L.off_tpre);
+  b = static_cast<char*>(ws_base);
+  w.counters = reinterpret_cast<uint32_t*>(b + L.off_counters);
+  w.tcount = reinterpret_cast<uint32_t*>(b + L.off_tcount);
+  w.tfill = reinterpret_cast<uint32_t*>(b + L.off_tfill);
+  w.bsum = reinterpret_cast<uint32_t*>(b + L.off_bsum);
   w.dcol = reinterpret_cast<float*>(b + L.off_dcol);
   w.dden = reinterpret_cast<float*>(b + L.off_dden);
+  w.pairs = reinterpret_cast<unsigned long long*>(b + L.off_pairs);
+  w.mtmp = reinterpret_cast<unsigned long long*>(b + L.off_mtmp);
   return w;
 }
 

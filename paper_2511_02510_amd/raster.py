@@ -182,31 +182,35 @@ def settings(tile=16, chunk=64, t_eps=1e-6, pair_capacity=0, chunk_bwd=0) -> LvS
 
 # --------------------------------------------------------------- C-ABI calls
 
-def query_sizes(ctx: Context, vox: Voxels, frame: Frame, st: LvSettings) -> int:
-    out = ctypes.c_uint64()
+def query_sizes(ctx: Context, vox: Voxels, frame: Frame, st: LvSettings):
+    """-> (workspace_bytes, saved_bytes)."""
+    ws, sv = ctypes.c_uint64(), ctypes.c_uint64()
     ctx.check(ctx.lib.lv_query_sizes(ctx.h, ctypes.byref(vox.struct), ctypes.byref(frame.struct),
-                                     ctypes.byref(st), ctypes.byref(out)), "lv_query_sizes")
-    return int(out.value)
+                                     ctypes.byref(st), ctypes.byref(ws), ctypes.byref(sv)),
+              "lv_query_sizes")
+    return int(ws.value), int(sv.value)
 
 
-def forward(ctx, vox, frame, st, workspace, rgb, depth, alpha, wmax, stream=None):
+def forward(ctx, vox, frame, st, workspace, saved, rgb, depth, alpha, wmax, stream=None):
     ctx.check(ctx.lib.lv_forward(ctx.h, ctypes.byref(vox.struct), ctypes.byref(frame.struct),
-                                 ctypes.byref(st), _p(workspace), _p(rgb), _p(depth), _p(alpha),
-                                 _p(wmax), _stream(stream)), "lv_forward")
+                                 ctypes.byref(st), _p(workspace), _p(saved), _p(rgb), _p(depth),
+                                 _p(alpha), _p(wmax), _stream(stream)), "lv_forward")
 
 
-def backward(ctx, vox, frame, st, workspace, d_rgb, d_depth, d_alpha, d_density, d_sh, stream=None):
+def backward(ctx, vox, frame, st, workspace, saved, d_rgb, d_depth, d_alpha, d_density, d_sh,
+             stream=None):
     ctx.check(ctx.lib.lv_backward(ctx.h, ctypes.byref(vox.struct), ctypes.byref(frame.struct),
-                                  ctypes.byref(st), _p(workspace), _p(d_rgb), _p(d_depth),
-                                  _p(d_alpha), _p(d_density), _p(d_sh), _stream(stream)),
-              "lv_backward")
+                                  ctypes.byref(st), _p(workspace), _p(saved), _p(d_rgb),
+                                  _p(d_depth), _p(d_alpha), _p(d_density), _p(d_sh),
+                                  _stream(stream)), "lv_backward")
 
 
-def check_overflow(ctx, vox, frame, st, workspace, stream=None):
-    """(fits, pairs_needed); synchronises the stream."""
+def check_overflow(ctx, vox, frame, st, saved, stream=None):
+    """(fits, pairs_needed) of the forward pass that filled `saved`;
+    synchronises the stream."""
     need = ctypes.c_uint64()
     s = ctx.lib.lv_check_overflow(ctx.h, ctypes.byref(vox.struct), ctypes.byref(frame.struct),
-                                  ctypes.byref(st), _p(workspace), ctypes.byref(need),
+                                  ctypes.byref(st), _p(saved), ctypes.byref(need),
                                   _stream(stream))
     if s == _abi.LV_ERR_CAPACITY:
         return False, int(need.value)
@@ -214,8 +218,9 @@ def check_overflow(ctx, vox, frame, st, workspace, stream=None):
     return True, int(need.value)
 
 
-def export_bins(ctx, vox, frame, st, workspace, stream=None):
-    """Host copies of the binning state: dict(tile_start, ids, codes, rects, vis)."""
+def export_bins(ctx, vox, frame, st, saved, stream=None):
+    """Host copies of the binning state a forward pass left in `saved`:
+    dict(tile_start, ids, codes, rects, vis)."""
     T = 0
     for (w, h) in frame.sizes:
         T += ((w + st.tile - 1) // st.tile) * ((h + st.tile - 1) // st.tile)
@@ -228,7 +233,7 @@ def export_bins(ctx, vox, frame, st, workspace, stream=None):
     ids = np.zeros(max(cap, 1), dtype=np.uint32)
     ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)
     ctx.check(ctx.lib.lv_export_bins(ctx.h, ctypes.byref(vox.struct), ctypes.byref(frame.struct),
-                                     ctypes.byref(st), _p(workspace), ptr(ts), ptr(ids), ptr(codes),
+                                     ctypes.byref(st), _p(saved), ptr(ts), ptr(ids), ptr(codes),
                                      ptr(rects), ptr(vis), _stream(stream)), "lv_export_bins")
     tot = min(int(ts[-1]), cap)
     return dict(tile_start=ts.astype(np.int64), ids=ids[:tot].astype(np.int64),
@@ -435,8 +440,11 @@ def read_timings(ctx):
 # -------------------------------------------------------- convenience layer
 
 class Renderer:
-    """Owns the workspace of one (voxels, frame, settings) shape and re-plans the
-    pair capacity when lv_check_overflow reports an overflow."""
+    """Owns the scratch workspace and a default saved-state buffer of one
+    (voxels, frame, settings) shape, and re-plans the pair capacity when
+    lv_check_overflow reports an overflow.  A forward pass writes its saved
+    state into `saved` (the renderer's own when None); the backward of that
+    pass must be given the same buffer and the settings the pass ran with."""
 
     def __init__(self, ctx: Context, vox: Voxels, frame: Frame, st: Optional[LvSettings] = None):
         self.ctx, self.vox, self.frame = ctx, vox, frame
@@ -447,8 +455,17 @@ class Renderer:
         self.checked = False
 
     def _alloc(self):
-        nbytes = query_sizes(self.ctx, self.vox, self.frame, self.st)
-        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.ctx.device)
+        ws, sv = query_sizes(self.ctx, self.vox, self.frame, self.st)
+        self.workspace = torch.empty(ws, dtype=torch.uint8, device=self.ctx.device)
+        self.saved_bytes = sv
+        self.saved = self.new_saved()
+
+    def new_saved(self) -> torch.Tensor:
+        """A fresh buffer for the saved state of one forward pass."""
+        return torch.empty(self.saved_bytes, dtype=torch.uint8, device=self.ctx.device)
+
+    def settings_copy(self) -> LvSettings:
+        return LvSettings.from_buffer_copy(self.st)
 
     def new_outputs(self):
         d = self.ctx.device
@@ -456,30 +473,44 @@ class Renderer:
         return (torch.empty(3 * P, device=d), torch.empty(P, device=d), torch.empty(P, device=d))
 
     def forward(self, rgb, depth, alpha, wmax, vox: Optional[Voxels] = None, stream=None,
-                verify: Optional[bool] = None):
+                verify: Optional[bool] = None, saved: Optional[torch.Tensor] = None):
+        """Returns the saved-state buffer the pass wrote (`saved`, or a larger
+        replacement after a capacity re-plan; the renderer's own if None)."""
         vox = vox or self.vox
+        own = saved is None
+        saved = self.saved if own else saved
         verify = verify or (verify is None and not self.checked)
         # a truncated pass composites without some occluders, so its weights
         # are not bounded by the true ones: keep w_max to restore on overflow
-        saved = wmax.clone() if (verify and wmax is not None) else None
-        forward(self.ctx, vox, self.frame, self.st, self.workspace, rgb, depth, alpha, wmax, stream)
+        keep = wmax.clone() if (verify and wmax is not None) else None
+        forward(self.ctx, vox, self.frame, self.st, self.workspace, saved, rgb, depth, alpha,
+                wmax, stream)
         if verify:
-            fits, need = check_overflow(self.ctx, vox, self.frame, self.st, self.workspace, stream)
+            fits, need = check_overflow(self.ctx, vox, self.frame, self.st, saved, stream)
             self.checked = True
             if not fits:
-                if saved is not None:
-                    wmax.copy_(saved)
+                if keep is not None:
+                    wmax.copy_(keep)
                 self.st.pair_capacity = min(need + need // 8 + 4096, (1 << 32) - 1)
                 self._alloc()
-                forward(self.ctx, vox, self.frame, self.st, self.workspace, rgb, depth, alpha,
-                        wmax, stream)
-                fits, need = check_overflow(self.ctx, vox, self.frame, self.st, self.workspace, stream)
+                saved = self.saved if own else self.new_saved()
+                forward(self.ctx, vox, self.frame, self.st, self.workspace, saved, rgb, depth,
+                        alpha, wmax, stream)
+                fits, need = check_overflow(self.ctx, vox, self.frame, self.st, saved, stream)
                 if not fits:
                     raise LiteVoxelError(_abi.LV_ERR_CAPACITY, f"{need} pairs do not fit")
+        return saved
 
     def backward(self, d_rgb, d_depth, d_alpha, d_density, d_sh, vox: Optional[Voxels] = None,
-                 stream=None):
-        backward(self.ctx, vox or self.vox, self.frame, self.st, self.workspace, d_rgb, d_depth,
+                 stream=None, saved: Optional[torch.Tensor] = None, st: Optional[LvSettings] = None):
+        """saved/st: the buffer and settings of the forward pass being
+        differentiated (default: the renderer's own)."""
+        st = st if st is not None else self.st
+        saved = self.saved if saved is None else saved
+        ws, _ = query_sizes(self.ctx, vox or self.vox, self.frame, st)
+        if ws > self.workspace.numel():
+            raise LiteVoxelError(_abi.LV_ERR_ARG, "workspace smaller than the pass needs")
+        backward(self.ctx, vox or self.vox, self.frame, st, self.workspace, saved, d_rgb, d_depth,
                  d_alpha, d_density, d_sh, stream)
 
 
@@ -488,19 +519,24 @@ class RasterizeFn(torch.autograd.Function):
     (rgb [3P], depth [P], alpha [P]); gradients with respect to the stored
     density values (through the layout's activation) and the SH.
 
-    The backward recomputes transmittance back to front inside lv_backward
-    from the per-pixel state lv_forward left in the renderer's workspace
-    (index of the last hit and the transmittance before it): no per-sample
-    state is kept.  w_max is max-accumulated into `wmax` (not differentiable).
+    Every forward pass gets a saved-state buffer of its own (tile lists,
+    records and the per-pixel index of the last hit with the transmittance
+    before it), kept on the autograd node with the settings it ran with, so
+    several passes on one renderer can be differentiated in any order.  The
+    backward recomputes transmittance back to front inside lv_backward from
+    that state: no per-sample state is kept.  w_max is max-accumulated into
+    `wmax` (not differentiable).
     """
 
     @staticmethod
     def forward(ctx, density, sh, renderer: Renderer, wmax: torch.Tensor):
         vox = renderer.vox.with_params(density.detach().contiguous(), sh.detach().contiguous())
         rgb, depth, alpha = renderer.new_outputs()
-        renderer.forward(rgb, depth, alpha, wmax, vox=vox)
+        saved = renderer.forward(rgb, depth, alpha, wmax, vox=vox, saved=renderer.new_saved())
         ctx.renderer = renderer
         ctx.vox = vox
+        ctx.saved_state = saved
+        ctx.st = renderer.settings_copy()
         ctx.mark_non_differentiable(wmax)
         return rgb, depth, alpha
 
@@ -513,7 +549,8 @@ class RasterizeFn(torch.autograd.Function):
         g_rgb = g_rgb.contiguous() if g_rgb is not None else torch.zeros(3 * r.frame.P, device=vox.density.device)
         g_depth = g_depth.contiguous() if g_depth is not None else None
         g_alpha = g_alpha.contiguous() if g_alpha is not None else None
-        r.backward(g_rgb, g_depth, g_alpha, d_density, d_sh, vox=vox)
+        r.backward(g_rgb, g_depth, g_alpha, d_density, d_sh, vox=vox, saved=ctx.saved_state,
+                   st=ctx.st)
         return d_density, d_sh, None, None
 
 

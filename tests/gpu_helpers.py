@@ -56,7 +56,7 @@ def run_gpu(ctx, scene, cams, tile=16, chunk=64, bg=(0.0, 0.0, 0.0), cap=0, grad
                alpha=alpha.cpu().numpy().astype(np.float64),
                wmax=wmax.cpu().numpy().astype(np.float64)[:vox.n])
     if export:
-        out["bins"] = m.export_bins(ctx, vox, frame, r.st, r.workspace)
+        out["bins"] = m.export_bins(ctx, vox, frame, r.st, r.saved)
     out["renderer"] = r
     return out
 

@@ -127,20 +127,28 @@ def test_validation_rejects_bad_arguments():
 
 def test_workspace_planning_scales_with_shapes():
     lib = _abi.lib()
-    out = ctypes.c_uint64()
-    sizes = []
+    out, sv = ctypes.c_uint64(), ctypes.c_uint64()
+    sizes, saved = [], []
     for cap in (0, 1000, 100000):
         vox, fr, st = _vox_frame(n=5000, w=100, h=70, views=2)
         st.pair_capacity = cap
         assert lib.lv_query_sizes(None, ctypes.byref(vox), ctypes.byref(fr), ctypes.byref(st),
-                                  ctypes.byref(out)) == _abi.LV_OK
+                                  ctypes.byref(out), ctypes.byref(sv)) == _abi.LV_OK
         sizes.append(out.value)
-    # 20 bytes of pair buffers per unit of capacity (key, id, merge scratch)
-    assert sizes[2] - sizes[1] == pytest.approx(20 * 99000, abs=3 * 256)
-    # records: 32 B per (view, voxel) + 12 B colour gradient, 48 B per voxel
-    assert sizes[0] > 5000 * 48 + 2 * 5000 * 44
+        saved.append(sv.value)
+    # scratch: 16 bytes of pair buffers per unit of capacity (key, merge
+    # scratch); saved state: 4 bytes (the per-tile voxel id)
+    assert sizes[2] - sizes[1] == pytest.approx(16 * 99000, abs=3 * 256)
+    assert saved[2] - saved[1] == pytest.approx(4 * 99000, abs=3 * 256)
+    # saved: records of 32 B per (view, voxel) and 48 B per voxel, 8 B per pixel;
+    # scratch: 12 B colour gradient per (view, voxel) and 32 B per voxel
+    P = 2 * 100 * 70
+    assert saved[0] >= 5000 * 48 + 2 * 5000 * 32 + 8 * P
+    assert sizes[0] >= 2 * 5000 * 12 + 5000 * 32
     assert lib.lv_query_sizes(None, ctypes.byref(vox), ctypes.byref(fr), ctypes.byref(st),
-                              None) == _abi.LV_ERR_ARG
+                              None, ctypes.byref(sv)) == _abi.LV_ERR_ARG
+    assert lib.lv_query_sizes(None, ctypes.byref(vox), ctypes.byref(fr), ctypes.byref(st),
+                              ctypes.byref(out), None) == _abi.LV_ERR_ARG
 
 
 def test_aux_workspace_sizes():

@@ -55,7 +55,7 @@ def ring(ctx):
                rgb=rgb.cpu().numpy().astype(np.float64), depth=depth.cpu().numpy().astype(np.float64),
                alpha=alpha.cpu().numpy().astype(np.float64), wmax=wmax.cpu().numpy().astype(np.float64),
                dd=dd.cpu().numpy().astype(np.float64), dsh=dsh.cpu().numpy().astype(np.float64),
-               bins=lv.export_bins(ctx, vox, frame, r.st, r.workspace))
+               bins=lv.export_bins(ctx, vox, frame, r.st, r.saved))
     return out
 
 

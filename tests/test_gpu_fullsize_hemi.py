@@ -58,7 +58,7 @@ def hemi():
                alpha=alpha.cpu().numpy().astype(np.float64), wmax=wmax.cpu().numpy(),
                dd=dd.cpu().numpy().astype(np.float64), dsh=dsh.cpu().numpy().astype(np.float64),
                bins=bins.cpu().numpy(), tau=tau.cpu().numpy(), prune=prune.cpu().numpy(),
-               tiles=lv.export_bins(ctx, vox, frame, r.st, r.workspace))
+               tiles=lv.export_bins(ctx, vox, frame, r.st, r.saved))
     del r, vox, frame
     ctx.close()
     return out

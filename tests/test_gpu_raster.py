@@ -155,13 +155,15 @@ def test_capacity_overflow_is_reported_and_replanned(ctx):
     vox = lv.Voxels.from_scene(scene, ctx.device)
     frame = lv.Frame(cams, ctx.device)
     st = lv.settings(pair_capacity=100)
-    ws = torch.empty(lv.query_sizes(ctx, vox, frame, st), dtype=torch.uint8, device=ctx.device)
+    ws_bytes, sv_bytes = lv.query_sizes(ctx, vox, frame, st)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=ctx.device)
+    sv = torch.empty(sv_bytes, dtype=torch.uint8, device=ctx.device)
     rgb = torch.empty(3 * frame.P, device=ctx.device)
     d = torch.empty(frame.P, device=ctx.device)
     a = torch.empty(frame.P, device=ctx.device)
     w = torch.zeros(vox.n, device=ctx.device)
-    lv.forward(ctx, vox, frame, st, ws, rgb, d, a, w)
-    fits, need = lv.check_overflow(ctx, vox, frame, st, ws)
+    lv.forward(ctx, vox, frame, st, ws, sv, rgb, d, a, w)
+    fits, need = lv.check_overflow(ctx, vox, frame, st, sv)
     assert not fits and need > 4096
     # the renderer re-plans and the result is exact
     g = run_gpu(ctx, scene, cams, cap=100, export=False)
