@@ -32,15 +32,15 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-# algorithmic bytes per launch of the composite kernels:
-# per (tile, voxel) pair: 4 B id + 48 B voxel record + 20 B view record;
-# per pixel: forward writes rgb 12 + depth 4 + alpha 4 + saved state 8,
-# backward reads the saved state 8 + d_rgb 12 and writes 11 reduced floats
-# (8 corner densities + 3 colour channels) per pair.
+# algorithmic bytes per launch of the composite kernels, the per-unit figures
+# of the hot-path byte model: per (tile, voxel) pair 4 B
+# id + a 59 B record gather (forward), plus 11 reduced 4-byte gradients
+# (backward: 107 B); per pixel 28 B (forward: rgb 12 + depth 4 + alpha 4 +
+# saved state 8; backward: saved state 8 + rgb/depth/alpha gradients 20).
 def composite_bytes(Q, P, which):
     if which == "composite_fwd":
-        return 72 * Q + 28 * P
-    return 72 * Q + 44 * Q + 20 * P
+        return 63 * Q + 28 * P
+    return 107 * Q + 28 * P
 
 
 PROFILE_MD = os.path.join(ROOT, "profiles", "composite_hbm_counters_ring1m.md")
@@ -204,11 +204,17 @@ def measure_workload(lv, ctx, name, tile, chunk, chunk_bwd, reps, warmup, quanti
         return ms
 
     fwd_ms = timed(fwd)
-    out = {"voxels": scene.n, "views": len(cams), "px": P, "fwd_ms": round(fwd_ms, 4),
-           "fwd_mp_s": round(P / fwd_ms / 1e3, 2)}
+    Q, M = lv.pass_stats(ctx, vox, frame, r.st, r.saved, stream=stream)
+    b_fwd, b_bwd = step_bytes(scene.n, M, Q, P, int(vox.sh.shape[0]))
+    out = {"voxels": scene.n, "views": len(cams), "px": P, "pairs": Q, "records": M,
+           "fwd_ms": round(fwd_ms, 4), "fwd_mp_s": round(P / fwd_ms / 1e3, 2),
+           "fwd_bytes": int(b_fwd),
+           "fwd_hbm_frac": round(b_fwd / (fwd_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     if name != "shell200k":          # that configuration is forward + w_max only
         step_ms = timed(step)
         out.update({"fwdbwd_ms": round(step_ms, 4), "fwdbwd_mp_s": round(P / step_ms / 1e3, 2),
+                    "bwd_bytes": int(b_bwd),
+                    "step_hbm_frac": round((b_fwd + b_bwd) / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                     "step": "fwd + lf_weight + l1 + bwd" + (" + depth quantile" if quantile else "")})
     log(f"[bench] {name}: {out} (scene generated in {gen_s:.1f} s)")
     del r, vox, frame, target
@@ -406,9 +412,7 @@ def main():
     fwd_roof = fwd_alg / (phases["composite_fwd"] * 1e-3) / 1e9
 
     # ---- whole-forward and whole-step HBM fractions (all phases)
-    bins = lv.export_bins(ctx, vox, frame, r.st, r.saved)
-    M = int(np.count_nonzero(bins["vis"]))
-    del bins
+    _, M = lv.pass_stats(ctx, vox, frame, r.st, r.saved, stream=stream)
     b_fwd, b_bwd = step_bytes(scene.n, M, Q, P, int(vox.sh.shape[0]))
     hbm = {"records": M, "fwd_bytes": int(b_fwd), "bwd_bytes": int(b_bwd),
            "fwd_frac": round(b_fwd / (fwd_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),

@@ -201,6 +201,15 @@ lv_status lv_check_overflow(lv_context* ctx, const lv_voxels* vox, const lv_fram
                             const lv_settings* st, const void* saved,
                             uint64_t* pairs_needed, hipStream_t stream);
 
+/* Synchronises the stream and reports the size of the forward pass that
+ * filled `saved`: pairs = (tile, voxel) pairs it produced (as
+ * lv_check_overflow), records = visible (view, voxel) records (voxels whose
+ * projected box covers at least one pixel centre of the view).  Either
+ * pointer may be NULL.  For measurement (bytes moved per pass). */
+lv_status lv_pass_stats(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
+                        const lv_settings* st, const void* saved, uint64_t* pairs,
+                        uint64_t* records, hipStream_t stream);
+
 /* Copies the binning state a forward pass left in `saved` to host buffers
  * (synchronises): tile_start [T+1] (T = total tiles, views in order,
  * row-major), ids [tile_start[T]] voxel ids in per-tile front-to-back order,

@@ -3,7 +3,7 @@ the LiteVoxel training loop (arXiv 2511.02510), behind the C-ABI declared in
 include/litevoxel.h.  The HIP library must be built (there is no fallback)."""
 from .raster import (  # noqa: F401
     Context, Voxels, Frame, Renderer, RasterizeFn, LiteVoxelError, rasterize, settings,
-    query_sizes, forward, backward, check_overflow, export_bins, lf_weight_workspace_size,
+    query_sizes, forward, backward, check_overflow, pass_stats, export_bins, lf_weight_workspace_size,
     lf_weight, l1_grad, gamma_schedule, quantile_workspace_size, depth_quantile, depth_bins,
     depth_cutoff, graph_begin, graph_end, graph_launch, graph_reset, autotune, tune_key, set_timing,
     read_timings,

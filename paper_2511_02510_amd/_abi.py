@@ -69,6 +69,8 @@ _SIGS = {
                               P, P, P, P, P, P]),
     "lv_check_overflow": (c_int32, [P, POINTER(LvVoxels), POINTER(LvFrame), POINTER(LvSettings),
                                     P, POINTER(c_uint64), P]),
+    "lv_pass_stats": (c_int32, [P, POINTER(LvVoxels), POINTER(LvFrame), POINTER(LvSettings), P,
+                                POINTER(c_uint64), POINTER(c_uint64), P]),
     "lv_export_bins": (c_int32, [P, POINTER(LvVoxels), POINTER(LvFrame), POINTER(LvSettings), P,
                                  P, P, P, P, P, P]),
     "lv_lf_weight_workspace_size": (c_uint64, [c_int32]),

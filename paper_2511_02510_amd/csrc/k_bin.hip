@@ -62,6 +62,7 @@ __global__ void k_setup(RasterArgs a) {
   if (blockIdx.x != 0) return;
   const int t = threadIdx.x;
   for (int k = t; k < kCounterWords; k += blockDim.x) a.ws.counters[k] = 0u;
+  for (int k = t; k < S_WORDS; k += blockDim.x) a.ws.status[k] = 0u;
   for (int v = t; v < a.V; v += blockDim.x)
     for (int ax = 0; ax < 3; ++ax)
       a.ws.views[v].cell[ax] = split_threshold(a.cams[v].o[ax], a.root_min[ax], a.root_size);
@@ -342,6 +343,11 @@ __global__ __launch_bounds__(kBinBlock) void k_preprocess(RasterArgs a) {
     }
     // --- tile counts, aggregated over the block
     const bool have = valid && visible;
+    {
+      // visible records of the block (reported by lv_pass_stats)
+      const int nvis = __syncthreads_count(have ? 1 : 0);
+      if (threadIdx.x == 0 && nvis) atomicAdd(&a.ws.status[S_RECORDS + sub], uint32_t(nvis));
+    }
     const uint32_t tx0 = (rec.xr & 0xFFFFu) >> sh_ts, tx1 = (rec.xr >> 16) >> sh_ts;
     const uint32_t ty0 = (rec.yr & 0xFFFFu) >> sh_ts, ty1 = (rec.yr >> 16) >> sh_ts;
     const TileWin win = block_tile_window(have, tx0, tx1, ty0, ty1);

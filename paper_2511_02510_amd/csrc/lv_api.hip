@@ -382,6 +382,25 @@ lv_status lv_check_overflow(lv_context* ctx, const lv_voxels* vox, const lv_fram
   return LV_OK;
 }
 
+lv_status lv_pass_stats(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
+                        const lv_settings* st, const void* saved, uint64_t* pairs,
+                        uint64_t* records, hipStream_t stream) {
+  if (!ctx) return LV_ERR_ARG;
+  lv::Layout L;
+  lv_status s = validate_all(ctx, vox, frame, st, &L);
+  if (s != LV_OK) return s;
+  if (!saved) return fail(ctx, LV_ERR_ARG, "saved is NULL");
+  LV_TRY(hipStreamSynchronize(stream), "synchronize");
+  uint32_t w[lv::S_WORDS] = {};
+  LV_TRY(hipMemcpy(w, static_cast<const char*>(saved) + L.off_status, sizeof(w),
+                   hipMemcpyDeviceToHost), "read status");
+  uint64_t rec = 0;
+  for (int k = 0; k < lv::kSpread; ++k) rec += w[lv::S_RECORDS + k];
+  if (pairs) *pairs = w[lv::S_PAIRS];
+  if (records) *records = rec;
+  return LV_OK;
+}
+
 lv_status lv_export_bins(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
                          const lv_settings* st, const void* saved, uint32_t* tile_start,
                          uint32_t* ids, uint64_t* codes, int32_t* rects, uint8_t* vis,

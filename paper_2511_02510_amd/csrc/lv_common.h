@@ -64,6 +64,7 @@ struct Rec {
 enum Status : int {
   S_PAIRS = 0,       // number of (tile, voxel) pairs (saturating below 2^32)
   S_OVERFLOW = 1,    // 1 if pairs > capacity
+  S_RECORDS = 16,    // [kSpread] visible (view, voxel) records, summed over the words
   S_WORDS = 64
 };
 

@@ -218,6 +218,16 @@ def check_overflow(ctx, vox, frame, st, saved, stream=None):
     return True, int(need.value)
 
 
+def pass_stats(ctx, vox, frame, st, saved, stream=None):
+    """(pairs, visible records) of the forward pass that filled `saved`;
+    synchronises the stream."""
+    q, m = ctypes.c_uint64(), ctypes.c_uint64()
+    ctx.check(ctx.lib.lv_pass_stats(ctx.h, ctypes.byref(vox.struct), ctypes.byref(frame.struct),
+                                    ctypes.byref(st), _p(saved), ctypes.byref(q), ctypes.byref(m),
+                                    _stream(stream)), "lv_pass_stats")
+    return int(q.value), int(m.value)
+
+
 def export_bins(ctx, vox, frame, st, saved, stream=None):
     """Host copies of the binning state a forward pass left in `saved`:
     dict(tile_start, ids, codes, rects, vis)."""
