@@ -46,15 +46,46 @@ struct Ray {
   float inv[3];
 };
 
+// Error-free transformations (contraction is off, so these are evaluated as
+// written): a + b = s + e and a * b = p + e exactly.
+__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+  s = a + b;
+  const float bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+__device__ __forceinline__ void two_prod(float a, float b, float& p, float& e) {
+  p = a * b;
+  e = fmaf(a, b, -p);
+}
+
+// Unit ray direction through the centre of pixel (px, py) (eq. 1), each
+// component with a small error relative to itself.  A chord's entry or exit
+// through a face of axis a lies at t = (plane - o_a) / d_a, so an absolute
+// error in a small d_a (a ray nearly parallel to that face) would move the
+// crossing by error / d_a.  The camera-space direction ((px + .5 - cx) / fx,
+// (py + .5 - cy) / fy, 1) is therefore carried as unevaluated float pairs
+// and R^T applied in compensated arithmetic: each world component is the
+// correctly rounded sum of its products up to a few ulps of itself, also
+// where the products cancel.  The normalisation then scales all three
+// components alike.  Per pixel, not per fragment.
 __device__ __forceinline__ Ray pixel_ray(const lv_camera& c, int px, int py) {
-  const float dcx = (float(px) + 0.5f - c.cx) / c.fx;
-  const float dcy = (float(py) + 0.5f - c.cy) / c.fy;
-  float d0 = c.R[0] * dcx + c.R[3] * dcy + c.R[6];
-  float d1 = c.R[1] * dcx + c.R[4] * dcy + c.R[7];
-  float d2 = c.R[2] * dcx + c.R[5] * dcy + c.R[8];
-  const float in = 1.0f / sqrtf(d0 * d0 + d1 * d1 + d2 * d2);
+  const float nx = (float(px) + 0.5f) - c.cx, ny = (float(py) + 0.5f) - c.cy;   // exact
+  const float xh = nx / c.fx, yh = ny / c.fy;
+  const float xl = fmaf(-xh, c.fx, nx) / c.fx, yl = fmaf(-yh, c.fy, ny) / c.fy;
+  float dd[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    float p1, e1, p2, e2, s1, e3, s2, e4;
+    two_prod(c.R[a], xh, p1, e1);
+    two_prod(c.R[3 + a], yh, p2, e2);
+    two_sum(p1, p2, s1, e3);
+    two_sum(s1, c.R[6 + a], s2, e4);
+    const float low = ((e1 + e2) + (e3 + e4)) + (c.R[a] * xl + c.R[3 + a] * yl);
+    dd[a] = s2 + low;
+  }
+  const float in = 1.0f / sqrtf(dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2]);
   Ray r;
-  r.d[0] = d0 * in; r.d[1] = d1 * in; r.d[2] = d2 * in;
+  r.d[0] = dd[0] * in; r.d[1] = dd[1] * in; r.d[2] = dd[2] * in;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     float x = r.d[a];
