@@ -233,6 +233,22 @@ lv_status lv_lf_weight(lv_context* ctx, const lv_frame* frame, const float* targ
                        float gamma, int32_t form, float eps, float* weight, void* workspace,
                        hipStream_t stream);
 
+/* lv_lf_weight for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same computation and results, with the workspace replaced by a static
+ * scratch array of the library (544 KiB per GPU, held until the process
+ * ends), so the caller passes only inputs and outputs.  At most
+ * LV_NOALLOC_MAX_VIEWS views (more: LV_ERR_ARG); the context's device must
+ * be current (else LV_ERR_STATE).  Every call on one GPU shares that GPU's
+ * scratch: calls that overlap in time on one GPU (other streams, other
+ * contexts, other host threads) race and give undefined weights; calls on
+ * one stream are ordered and safe.  Allocates nothing; each call clears the
+ * scratch it needs on the stream before using it. */
+#define LV_NOALLOC_MAX_VIEWS 64
+lv_status lv_lf_weight_noalloc(lv_context* ctx, const lv_frame* frame, const float* target,
+                               float gamma, int32_t form, float eps, float* weight,
+                               hipStream_t stream);
+
 /* Weighted L1 (eq. 10 with rho = mean over channels of |r|): writes
  * loss[v] = (1/|P_v|) sum_p w~(p) (1/3) sum_ch |C - I| per view (device
  * [n_views], overwritten) and d_rgb = w~ sign(C - I) / (3 |P_v|). */

@@ -75,6 +75,7 @@ _SIGS = {
                                  P, P, P, P, P, P]),
     "lv_lf_weight_workspace_size": (c_uint64, [c_int32]),
     "lv_lf_weight": (c_int32, [P, POINTER(LvFrame), P, c_float, c_int32, c_float, P, P, P]),
+    "lv_lf_weight_noalloc": (c_int32, [P, POINTER(LvFrame), P, c_float, c_int32, c_float, P, P]),
     "lv_l1_grad": (c_int32, [P, POINTER(LvFrame), P, P, P, P, P, P]),
     "lv_gamma_schedule": (c_float, [c_float, c_float, c_float, c_float, c_float]),
     "lv_quantile_workspace_size": (c_uint64, [c_int64, c_int32]),

@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -38,8 +39,39 @@ hipError_t run_prune_guard(const RasterArgs& a, const uint8_t* bins, const float
                            uint8_t* prune, uint32_t* n_pruned, hipStream_t s);
 }  // namespace lv
 
+namespace {
+// Static scratch of lv_lf_weight_noalloc: the loss-weight workspace of at
+// most kNoAllocViews views (selection histograms and states, per-view weight
+// sums), one copy per GPU, held until the process ends.  In host code the
+// array's name is not a device address: kernels get the address that
+// hipGetSymbolAddress returns for the current device, looked up once per
+// device by lv_create and kept in g_scratch_ptr.
+constexpr int kNoAllocViews = LV_NOALLOC_MAX_VIEWS;
+constexpr size_t kNoAllocBytes = 544 * 1024;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// device address of `scratch` on hip_device (the current device), or NULL
+void* scratch_address(int hip_device) {
+  if (hip_device < 0 || hip_device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[hip_device]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_scratch_ptr[hip_device] = ptr;
+  }
+  return g_scratch_ptr[hip_device];
+}
+}  // namespace
+
 struct lv_context {
   int device = 0;
+  void* scratch = nullptr;   // this device's copy of the static scratch
   std::string err;
   bool timing = false;
   bool capturing = false;
@@ -247,6 +279,7 @@ lv_status lv_create(lv_context** out, int hip_device) {
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return LV_ERR_UNSUPPORTED;
   lv_context* c = new lv_context();
   c->device = hip_device;
+  c->scratch = scratch_address(hip_device);   // the device is current here
   *out = c;
   return LV_OK;
 }
@@ -460,6 +493,33 @@ lv_status lv_lf_weight(lv_context* ctx, const lv_frame* frame, const float* targ
     return fail(ctx, LV_ERR_ARG, "gamma must be finite and eps >= 0");
   LV_TRY(lv::run_lf_weight(frame->cams_dev, frame->cams_host, frame->n_views, target, gamma, form,
                            eps, weight, workspace, stream), "lf_weight");
+  return LV_OK;
+}
+
+lv_status lv_lf_weight_noalloc(lv_context* ctx, const lv_frame* frame, const float* target,
+                               float gamma, int32_t form, float eps, float* weight,
+                               hipStream_t stream) {
+  if (!ctx) return LV_ERR_ARG;
+  lv_status s = check_frame(ctx, frame);
+  if (s != LV_OK) return s;
+  if (frame->n_views > kNoAllocViews)
+    return fail(ctx, LV_ERR_ARG,
+                "n_views=%d exceeds the %d views the static scratch holds (use lv_lf_weight)",
+                frame->n_views, kNoAllocViews);
+  if (!target || !weight) return fail(ctx, LV_ERR_ARG, "target/weight NULL");
+  if (form != 0 && form != 1) return fail(ctx, LV_ERR_ARG, "form must be 0 or 1");
+  if (!std::isfinite(gamma) || !std::isfinite(eps) || eps < 0.0f)
+    return fail(ctx, LV_ERR_ARG, "gamma must be finite and eps >= 0");
+  if (lv::loss_ws_bytes(frame->n_views) > kNoAllocBytes)
+    return fail(ctx, LV_ERR_UNSUPPORTED, "static scratch smaller than the loss workspace");
+  int dev = -1;
+  LV_TRY(hipGetDevice(&dev), "current device");
+  if (dev != ctx->device)
+    return fail(ctx, LV_ERR_STATE, "current device %d is not the context's device %d", dev,
+                ctx->device);
+  if (!ctx->scratch) return fail(ctx, LV_ERR_HIP, "static scratch address unavailable");
+  LV_TRY(lv::run_lf_weight(frame->cams_dev, frame->cams_host, frame->n_views, target, gamma, form,
+                           eps, weight, ctx->scratch, stream), "lf_weight_noalloc");
   return LV_OK;
 }
 

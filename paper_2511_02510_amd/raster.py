@@ -261,6 +261,14 @@ def lf_weight(ctx, frame, target, gamma, form, eps, weight, workspace, stream=No
                                    _stream(stream)), "lv_lf_weight")
 
 
+def lf_weight_noalloc(ctx, frame, target, gamma, form, eps, weight, stream=None):
+    """lf_weight on the library's static scratch (no workspace argument; at
+    most 64 views; calls overlapping on one GPU race)."""
+    ctx.check(ctx.lib.lv_lf_weight_noalloc(ctx.h, ctypes.byref(frame.struct), _p(target),
+                                           float(gamma), int(form), float(eps), _p(weight),
+                                           _stream(stream)), "lv_lf_weight_noalloc")
+
+
 def l1_grad(ctx, frame, rgb, target, weight, loss, d_rgb, stream=None):
     ctx.check(ctx.lib.lv_l1_grad(ctx.h, ctypes.byref(frame.struct), _p(rgb), _p(target),
                                  _p(weight), _p(loss), _p(d_rgb), _stream(stream)), "lv_l1_grad")
