@@ -204,8 +204,10 @@ lv_status lv_check_overflow(lv_context* ctx, const lv_voxels* vox, const lv_fram
 /* Synchronises the stream and reports the size of the forward pass that
  * filled `saved`: pairs = (tile, voxel) pairs it produced (as
  * lv_check_overflow), records = visible (view, voxel) records (voxels whose
- * projected box covers at least one pixel centre of the view).  Either
- * pointer may be NULL.  For measurement (bytes moved per pass). */
+ * projected box covers at least one pixel centre of the view), counted by
+ * one pass over the view records when `records` is not NULL (that pass
+ * allocates and frees 8 bytes of device memory).  Either pointer may be NULL.
+ * For measurement (bytes moved per pass). */
 lv_status lv_pass_stats(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
                         const lv_settings* st, const void* saved, uint64_t* pairs,
                         uint64_t* records, hipStream_t stream);

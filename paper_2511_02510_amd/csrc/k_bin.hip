@@ -343,11 +343,6 @@ __global__ __launch_bounds__(kBinBlock) void k_preprocess(RasterArgs a) {
     }
     // --- tile counts, aggregated over the block
     const bool have = valid && visible;
-    {
-      // visible records of the block (reported by lv_pass_stats)
-      const int nvis = __syncthreads_count(have ? 1 : 0);
-      if (threadIdx.x == 0 && nvis) atomicAdd(&a.ws.status[S_RECORDS + sub], uint32_t(nvis));
-    }
     const uint32_t tx0 = (rec.xr & 0xFFFFu) >> sh_ts, tx1 = (rec.xr >> 16) >> sh_ts;
     const uint32_t ty0 = (rec.yr & 0xFFFFu) >> sh_ts, ty1 = (rec.yr >> 16) >> sh_ts;
     const TileWin win = block_tile_window(have, tx0, tx1, ty0, ty1);
@@ -395,6 +390,31 @@ hipError_t launch_preprocess(const RasterArgs& a, hipStream_t s) {
     default: hipLaunchKernelGGL(LV_PRE(3), dim3(blocks), dim3(kBinBlock), 0, s, a); break;
   }
 #undef LV_PRE
+  return hipGetLastError();
+}
+
+// Visible (view, voxel) records of a forward pass (binned flag set), for
+// statistics only: one pass over the records' flag words, one atomic per block.
+__global__ __launch_bounds__(256) void k_count_records(const Rec* rec, uint64_t nrec,
+                                                       unsigned long long* out) {
+  uint32_t c = 0;
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < nrec; i += stride)
+    c += (rec[i].flags & 8u) ? 1u : 0u;
+  __shared__ uint32_t s_c;
+  if (threadIdx.x == 0) s_c = 0u;
+  __syncthreads();
+  atomicAdd(&s_c, c);
+  __syncthreads();
+  if (threadIdx.x == 0 && s_c) atomicAdd(out, (unsigned long long)s_c);
+}
+
+hipError_t launch_count_records(const Rec* rec, uint64_t nrec, unsigned long long* out,
+                                hipStream_t s) {
+  if (nrec == 0) return hipSuccess;
+  uint64_t blocks = (nrec + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_count_records, dim3(uint32_t(blocks)), dim3(256), 0, s, rec, nrec, out);
   return hipGetLastError();
 }
 

@@ -427,10 +427,23 @@ lv_status lv_pass_stats(lv_context* ctx, const lv_voxels* vox, const lv_frame* f
   uint32_t w[lv::S_WORDS] = {};
   LV_TRY(hipMemcpy(w, static_cast<const char*>(saved) + L.off_status, sizeof(w),
                    hipMemcpyDeviceToHost), "read status");
-  uint64_t rec = 0;
-  for (int k = 0; k < lv::kSpread; ++k) rec += w[lv::S_RECORDS + k];
   if (pairs) *pairs = w[lv::S_PAIRS];
-  if (records) *records = rec;
+  if (records) {
+    // counted on demand (a diagnostic call, outside any captured sequence)
+    unsigned long long* cnt = nullptr;
+    LV_TRY(hipMalloc(&cnt, sizeof(*cnt)), "record counter");
+    unsigned long long h = 0;
+    hipError_t e = hipMemsetAsync(cnt, 0, sizeof(*cnt), stream);
+    if (e == hipSuccess)
+      e = lv::launch_count_records(reinterpret_cast<const lv::Rec*>(
+                                       static_cast<const char*>(saved) + L.off_rec),
+                                   uint64_t(L.n) * uint64_t(L.V), cnt, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e == hipSuccess) e = hipMemcpy(&h, cnt, sizeof(h), hipMemcpyDeviceToHost);
+    (void)hipFree(cnt);
+    LV_TRY(e, "count records");
+    *records = h;
+  }
   return LV_OK;
 }
 

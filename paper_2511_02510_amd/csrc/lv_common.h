@@ -64,7 +64,6 @@ struct Rec {
 enum Status : int {
   S_PAIRS = 0,       // number of (tile, voxel) pairs (saturating below 2^32)
   S_OVERFLOW = 1,    // 1 if pairs > capacity
-  S_RECORDS = 16,    // [kSpread] visible (view, voxel) records, summed over the words
   S_WORDS = 64
 };
 
@@ -360,6 +359,8 @@ struct FillSet {   // word ranges filled by one launch
 };
 hipError_t launch_fill_set(const FillSet& f, hipStream_t s);
 hipError_t launch_preprocess(const RasterArgs& a, hipStream_t s);
+hipError_t launch_count_records(const Rec* rec, uint64_t nrec, unsigned long long* out,
+                                hipStream_t s);
 hipError_t launch_scan_tiles(const RasterArgs& a, uint32_t nblk, hipStream_t s);
 hipError_t launch_emit(const RasterArgs& a, hipStream_t s);
 hipError_t launch_sort(const RasterArgs& a, hipStream_t s);
