@@ -7,6 +7,11 @@ Parts and the passages they follow:
   raster_ref.cpp  rays, voxels, compositing, w_max           Sec. III, eq. 1-5
                   analytic adjoint of eq. 2-4 (ref_backward)
                   binary32 binning + visibility code (key path)
+  raster_ref.cpp  auxiliary channels (ref_render_aux,           eq. 6, 17 (named
+                  ref_backward_aux): distortion, normal        terms; readings
+                                                               in the file)
+  aux.py          transmittance concentration, depth-normal
+                  consistency, distortion mean (image terms)   eq. 6, 17
   loss.py         inverse-Sobel weight, mean normalisation,
                   gamma(t) ramp, weighted L1 and its gradient  Sec. IV-B, eq. 7-10
   quantile.py     depth proxy, eq. 14 normalisation, per-bin
@@ -60,6 +65,12 @@ def lib():
         L.ref_backward.argtypes = [i64, i32, P, f64, P, P, P, P, i32, P, P, P, P, i64,
                                    P, P, P, P, P, i32]
         L.ref_backward.restype = i32
+        L.ref_render_aux.argtypes = [i64, i32, P, f64, P, P, P, P, i32, P, P, P,
+                                     P, P, P, P, P, P, i32]
+        L.ref_render_aux.restype = i32
+        L.ref_backward_aux.argtypes = [i64, i32, P, f64, P, P, P, P, i32, P, P, P,
+                                       P, P, P, P, P, P, P, i32]
+        L.ref_backward_aux.restype = i32
         L.ref_footprint_pixels.argtypes = [i64, P, f64, P, P, i32, P, P, P, i64, P, i64]
         L.ref_footprint_pixels.restype = i64
         L.ref_voxel_colours.argtypes = [i64, i32, P, f64, P, P, P, i32, P, P, P, P]
@@ -167,6 +178,43 @@ def backward(scene, cams, g_rgb, g_depth=None, g_alpha=None, bg=(0.0, 0.0, 0.0),
     lib().ref_backward(*S.args(), len(cams), _p(c), _p(wh), _p(bgv), _p(pl),
                        0 if pl is None else pl.shape[0], _p(g_rgb), _p(gd), _p(ga),
                        _p(dd), _p(dsh), int(threads))
+    return dd, dsh
+
+
+def render_aux(scene, cams, bg=(0.0, 0.0, 0.0), wmax_in=None, threads=0):
+    """FP64 forward with the auxiliary channels: render()'s outputs plus
+    dist [P] (per-pixel distortion) and normal [3P] (rendered normal, rgb
+    layout: view blocks [3, H, W]); see raster_ref.cpp for the readings."""
+    S = _SceneArrays(scene)
+    c, wh = cams_arrays(cams)
+    off = pix_offsets(cams)
+    P = int(off[-1])
+    rgb = np.zeros(3 * P, dtype=np.float64)
+    depth = np.zeros(P, dtype=np.float64)
+    alpha = np.zeros(P, dtype=np.float64)
+    dist = np.zeros(P, dtype=np.float64)
+    normal = np.zeros(3 * P, dtype=np.float64)
+    wmax = np.zeros(S.n, dtype=np.float64) if wmax_in is None else \
+        np.ascontiguousarray(wmax_in, dtype=np.float64).copy()
+    bgv = np.ascontiguousarray(bg, dtype=np.float64)
+    lib().ref_render_aux(*S.args(), len(cams), _p(c), _p(wh), _p(bgv), _p(rgb), _p(depth),
+                         _p(alpha), _p(dist), _p(normal), _p(wmax), int(threads))
+    return dict(rgb=rgb, views=split_views(rgb, cams), depth=depth, alpha=alpha, dist=dist,
+                normal=normal, wmax=wmax)
+
+
+def backward_aux(scene, cams, g_rgb, g_depth=None, g_alpha=None, g_dist=None, g_normal=None,
+                 bg=(0.0, 0.0, 0.0), threads=0):
+    """FP64 analytic gradient with the auxiliary channels -> (d_density, d_sh)."""
+    S = _SceneArrays(scene)
+    c, wh = cams_arrays(cams)
+    f = lambda a: None if a is None else np.ascontiguousarray(a, dtype=np.float64).ravel()
+    g_rgb, gd, ga, gl, gn = f(g_rgb), f(g_depth), f(g_alpha), f(g_dist), f(g_normal)
+    dd = np.zeros((8, S.n), dtype=np.float64)
+    dsh = np.zeros((3 * (S.deg + 1) ** 2, S.n), dtype=np.float64)
+    bgv = np.ascontiguousarray(bg, dtype=np.float64)
+    lib().ref_backward_aux(*S.args(), len(cams), _p(c), _p(wh), _p(bgv), _p(g_rgb), _p(gd),
+                           _p(ga), _p(gl), _p(gn), _p(dd), _p(dsh), int(threads))
     return dd, dsh
 
 

@@ -315,6 +315,49 @@ PixLoc locate(const std::vector<int64_t>& off, const std::vector<Cam>& cams, int
   return PixLoc{v, int(r % cams[v].W), int(r / cams[v].W)};
 }
 
+// ------------------------------------------------------- auxiliary channels
+// Render channels behind the auxiliary terms of the training objective that
+// the paper names (eq. 6 and eq. 17: ray-space distortion, depth-normal
+// consistency; transmittance concentration acts on alpha and needs none).
+// The paper defines none of them; readings used here:
+//   distortion  Ld = sum_i sum_j w_i w_j |tm_i - tm_j| + (1/3) sum_i w_i^2 l_i
+//               over the hits of the ray, tm the chord midpoint, l the chord
+//               length (the segment-based distortion of Mip-NeRF 360 with
+//               ray distance as the coordinate);
+//   normal      N = sum_k w_k n_k, n_v = -g / |g| with g the gradient of the
+//               voxel's trilinear density at the cell centre (0 when g = 0).
+
+// u = gradient of the trilinear density at the cell centre in cell units:
+// u_a = 1/4 sum over the cell's 4 edges along axis a of (upper - lower corner
+// value), the exact derivative there.  n = -u / |u| (0 if u = 0).
+void voxel_normal(const Scene& sc, int64_t v, double u[3], double& ulen, double nrm[3]) {
+  double q = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    double s = 0.0;
+    for (int c = 0; c < 8; ++c) s += (((c >> a) & 1) ? 1.0 : -1.0) * sc.density[c * sc.n + v];
+    u[a] = 0.25 * s;
+    q += u[a] * u[a];
+  }
+  ulen = std::sqrt(q);
+  for (int a = 0; a < 3; ++a) nrm[a] = ulen > 0.0 ? -u[a] / ulen : 0.0;
+}
+
+// weights, chord midpoints and lengths of a pixel's hits (front to back),
+// and the transmittance after each hit
+void hit_weights(const std::vector<Hit>& hits, std::vector<double>& w, std::vector<double>& tm,
+                 std::vector<double>& len, std::vector<double>& Ta) {
+  size_t K = hits.size();
+  w.assign(K, 0.0); tm.assign(K, 0.0); len.assign(K, 0.0); Ta.assign(K, 0.0);
+  double T = 1.0;
+  for (size_t k = 0; k < K; ++k) {
+    w[k] = T * hits[k].alpha;
+    tm[k] = 0.5 * (hits[k].tin + hits[k].tout);
+    len[k] = hits[k].tout - hits[k].tin;
+    T *= std::exp(-hits[k].tau);
+    Ta[k] = T;
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -371,6 +414,170 @@ int ref_render(int64_t n, int deg, const float* root_min, double root_size,
       depth[g] = dep;
       alpha[g] = 1.0 - T;
       if (n_hits) n_hits[g] = int32_t(hits.size());
+    }
+  }
+  return 0;
+}
+
+// Forward render with the auxiliary channels: everything ref_render writes
+// (rgb, depth, alpha, wmax) plus dist [P] (the distortion Ld of each pixel)
+// and normal (the rendered normal N, per view [3][H][W] at 3*off[v]).
+int ref_render_aux(int64_t n, int deg, const float* root_min, double root_size,
+                   const uint16_t* ijk, const uint8_t* level, const double* density,
+                   const double* sh, int n_views, const float* cams, const int32_t* wh,
+                   const double* bg, double* rgb, double* depth, double* alpha, double* dist,
+                   double* normal, double* wmax, int n_threads) {
+  Scene sc = make_scene(n, deg, root_min, root_size, ijk, level, density, sh);
+  auto C = load_cams(n_views, cams, wh);
+  auto off = pix_offsets(C);
+  std::vector<ViewBins> bins(n_views);
+  for (int i = 0; i < n_views; ++i) bins[i] = bin_view(sc, C[i]);
+  int64_t total = off[n_views];
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel
+  {
+    std::vector<Hit> hits;
+    std::vector<double> w, tm, len, Ta;
+#pragma omp for schedule(dynamic, 256)
+    for (int64_t g = 0; g < total; ++g) {
+      PixLoc pl = locate(off, C, g);
+      const Cam& cam = C[pl.view];
+      trace(sc, cam, bins[pl.view], pl.px, pl.py, hits, false);
+      hit_weights(hits, w, tm, len, Ta);
+      size_t K = hits.size();
+      double TK = K ? Ta[K - 1] : 1.0;
+      double acc[3] = {0, 0, 0}, dep = 0.0, nr[3] = {0, 0, 0}, ld = 0.0;
+      for (size_t k = 0; k < K; ++k) {
+        double c[3], raw[3], Y[16], u[3], ul, nv[3];
+        voxel_colour(sc, hits[k].v, cam.o, c, raw, Y);
+        voxel_normal(sc, hits[k].v, u, ul, nv);
+        for (int ch = 0; ch < 3; ++ch) { acc[ch] += w[k] * c[ch]; nr[ch] += w[k] * nv[ch]; }
+        dep += w[k] * tm[k];
+        if (wmax) atomic_max_double(&wmax[hits[k].v], w[k]);
+        for (size_t j = 0; j < K; ++j) ld += w[k] * w[j] * std::fabs(tm[k] - tm[j]);
+        ld += w[k] * w[k] * len[k] / 3.0;
+      }
+      int64_t local = g - off[pl.view];
+      int64_t npv = int64_t(cam.W) * cam.H;
+      for (int ch = 0; ch < 3; ++ch) {
+        rgb[3 * off[pl.view] + ch * npv + local] = acc[ch] + TK * bg[ch];
+        normal[3 * off[pl.view] + ch * npv + local] = nr[ch];
+      }
+      depth[g] = dep;
+      alpha[g] = 1.0 - TK;
+      dist[g] = ld;
+    }
+  }
+  return 0;
+}
+
+// Analytic gradient with the auxiliary channels.  Upstream per pixel:
+// g_rgb (rgb layout), g_depth, g_alpha, g_dist [P], g_normal (rgb layout);
+// every pointer but g_rgb may be NULL.  With G_k = dL/dw_k (colour, depth,
+// distortion and normal terms),
+//   dL/dtau_k = T_k G_k - sum_{j>k} w_j G_j + T_K (g_A - g_C . bg)
+// (dw_k/dtau_k = T_k, dw_j/dtau_k = -w_j for j > k), spread over the corner
+// densities by the chord integrals of their trilinear weights; the normal
+// term adds w_k g_N to dL/dn_v, carried through n = -u/|u| and u (linear in
+// the corner values) to the densities.  Outputs overwritten: d_density
+// [8][n], d_sh [3(deg+1)^2][n].
+int ref_backward_aux(int64_t n, int deg, const float* root_min, double root_size,
+                     const uint16_t* ijk, const uint8_t* level, const double* density,
+                     const double* sh, int n_views, const float* cams, const int32_t* wh,
+                     const double* bg, const double* g_rgb, const double* g_depth,
+                     const double* g_alpha, const double* g_dist, const double* g_normal,
+                     double* d_density, double* d_sh, int n_threads) {
+  Scene sc = make_scene(n, deg, root_min, root_size, ijk, level, density, sh);
+  auto C = load_cams(n_views, cams, wh);
+  auto off = pix_offsets(C);
+  std::vector<ViewBins> bins(n_views);
+  for (int i = 0; i < n_views; ++i) bins[i] = bin_view(sc, C[i]);
+  int nb = (deg + 1) * (deg + 1);
+  std::memset(d_density, 0, sizeof(double) * 8 * n);
+  std::memset(d_sh, 0, sizeof(double) * 3 * nb * n);
+  std::vector<double> d_col(size_t(n_views) * n * 3, 0.0);
+  std::vector<double> d_nrm(size_t(n) * 3, 0.0);
+  int64_t total = off[n_views];
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel
+  {
+    std::vector<Hit> hits;
+    std::vector<double> w, tm, len, Ta, G;
+#pragma omp for schedule(dynamic, 256)
+    for (int64_t g = 0; g < total; ++g) {
+      PixLoc pl = locate(off, C, g);
+      const Cam& cam = C[pl.view];
+      int64_t local = g - off[pl.view];
+      int64_t npv = int64_t(cam.W) * cam.H;
+      double gC[3], gN[3] = {0, 0, 0};
+      for (int ch = 0; ch < 3; ++ch) {
+        gC[ch] = g_rgb[3 * off[pl.view] + ch * npv + local];
+        if (g_normal) gN[ch] = g_normal[3 * off[pl.view] + ch * npv + local];
+      }
+      double gD = g_depth ? g_depth[g] : 0.0;
+      double gA = g_alpha ? g_alpha[g] : 0.0;
+      double gL = g_dist ? g_dist[g] : 0.0;
+      trace(sc, cam, bins[pl.view], pl.px, pl.py, hits, true);
+      hit_weights(hits, w, tm, len, Ta);
+      size_t K = hits.size();
+      double TK = K ? Ta[K - 1] : 1.0;
+      G.assign(K, 0.0);
+      for (size_t k = 0; k < K; ++k) {
+        double c[3], raw[3], Y[16], u[3], ul, nv[3];
+        voxel_colour(sc, hits[k].v, cam.o, c, raw, Y);
+        voxel_normal(sc, hits[k].v, u, ul, nv);
+        double Gk = gD * tm[k];
+        for (int ch = 0; ch < 3; ++ch) Gk += gC[ch] * c[ch] + gN[ch] * nv[ch];
+        double dd = 0.0;
+        for (size_t j = 0; j < K; ++j) dd += w[j] * std::fabs(tm[k] - tm[j]);
+        Gk += gL * (2.0 * dd + 2.0 * w[k] * len[k] / 3.0);
+        G[k] = Gk;
+        for (int ch = 0; ch < 3; ++ch) {
+#pragma omp atomic
+          d_col[(size_t(pl.view) * n + hits[k].v) * 3 + ch] += w[k] * gC[ch];
+#pragma omp atomic
+          d_nrm[size_t(hits[k].v) * 3 + ch] += w[k] * gN[ch];
+        }
+      }
+      double base = TK * (gA - (gC[0] * bg[0] + gC[1] * bg[1] + gC[2] * bg[2]));
+      for (size_t k = 0; k < K; ++k) {
+        double later = 0.0;
+        for (size_t j = k + 1; j < K; ++j) later += w[j] * G[j];
+        double dtau = Ta[k] * G[k] - later + base;
+        for (int c = 0; c < 8; ++c) {
+#pragma omp atomic
+          d_density[c * n + hits[k].v] += dtau * hits[k].beta[c];
+        }
+      }
+    }
+  }
+  // normal -> corner densities: dn/du = -(I - u u^T / |u|^2) / |u|,
+  // du_a/dsigma_c = +1/4 (corner bit a set) or -1/4
+#pragma omp parallel for schedule(static)
+  for (int64_t v = 0; v < n; ++v) {
+    const double* gn = &d_nrm[size_t(v) * 3];
+    if (gn[0] == 0.0 && gn[1] == 0.0 && gn[2] == 0.0) continue;
+    double u[3], ul, nv[3];
+    voxel_normal(sc, v, u, ul, nv);
+    if (!(ul > 0.0)) continue;
+    double ug = (u[0] * gn[0] + u[1] * gn[1] + u[2] * gn[2]) / (ul * ul);
+    double gu[3];
+    for (int a = 0; a < 3; ++a) gu[a] = -(gn[a] - u[a] * ug) / ul;
+    for (int c = 0; c < 8; ++c)
+      for (int a = 0; a < 3; ++a) d_density[c * n + v] += 0.25 * (((c >> a) & 1) ? 1.0 : -1.0) * gu[a];
+  }
+  // colour -> SH coefficients (through the clamp at zero)
+#pragma omp parallel for schedule(static)
+  for (int64_t v = 0; v < n; ++v) {
+    for (int vi = 0; vi < n_views; ++vi) {
+      const double* dc = &d_col[(size_t(vi) * n + v) * 3];
+      if (dc[0] == 0.0 && dc[1] == 0.0 && dc[2] == 0.0) continue;
+      double c[3], raw[3], Y[16];
+      voxel_colour(sc, v, C[vi].o, c, raw, Y);
+      for (int ch = 0; ch < 3; ++ch) {
+        if (!(raw[ch] > 0.0)) continue;
+        for (int i = 0; i < nb; ++i) d_sh[(i * 3 + ch) * n + v] += Y[i] * dc[ch];
+      }
     }
   }
   return 0;
