@@ -194,6 +194,48 @@ lv_status lv_backward(lv_context* ctx, const lv_voxels* vox, const lv_frame* fra
                       const float* d_rgb, const float* d_depth, const float* d_alpha,
                       float* d_density, float* d_sh, hipStream_t stream);
 
+/* ------------------------------------------------------- auxiliary channels
+ * Render channels for the auxiliary terms of the training objective (eq. 6
+ * and eq. 17 name ray-space distortion and depth-normal consistency among
+ * them without defining them; readings used):
+ *   dist [P]    per pixel  sum_i sum_j w_i w_j |tm_i - tm_j| + 1/3 sum_i w_i^2 l_i
+ *               over the composited hits (tm = (t_in + t_out)/2, l = t_out - t_in);
+ *   normal      per pixel  N = sum_k w_k n_k, rgb layout ([3][H][W] per view),
+ *               n_v = -u/|u| with u the gradient of voxel v's trilinear
+ *               density at the cell centre (n_v = 0 when u = 0).
+ * lv_forward_aux is lv_forward that also writes dist and normal (either may
+ * be NULL; the rest as lv_forward, the same `saved` for the backward).
+ * lv_backward_aux is lv_backward with the upstream gradients of the new
+ * channels: d_dist [P] and d_normal (rgb layout), each nullable; d_dist
+ * needs depth_fwd, the depth lv_forward_aux wrote for this pass (the
+ * backward recovers the depth accumulated before each hit from it), else
+ * LV_ERR_ARG.  With both NULL it equals lv_backward. */
+lv_status lv_forward_aux(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
+                         const lv_settings* st, void* workspace, void* saved, float* rgb,
+                         float* depth, float* alpha, float* wmax, float* dist, float* normal,
+                         hipStream_t stream);
+lv_status lv_backward_aux(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
+                          const lv_settings* st, void* workspace, const void* saved,
+                          const float* d_rgb, const float* d_depth, const float* d_alpha,
+                          const float* depth_fwd, const float* d_dist, const float* d_normal,
+                          float* d_density, float* d_sh, hipStream_t stream);
+
+/* Image-space auxiliary terms per view (eq. 6 and 17; readings used):
+ *   loss[3v + 0] = lam_tc / |P_v| sum_p A (1 - A)        (transmittance concentration)
+ *   loss[3v + 1] = lam_n / |I_v| sum_{p in I_v} (A - N . m)  (depth-normal consistency)
+ *   loss[3v + 2] = lam_d / |P_v| sum_p dist              (distortion)
+ * with I_v the interior pixels (1 <= x <= W-2, 1 <= y <= H-2; none when W or
+ * H < 3) and m the unit normal of the surface of the depth channel: X = o +
+ * D d (d the pixel's unit ray), m = normalise((X(x,y+1) - X(x,y-1)) x
+ * (X(x+1,y) - X(x-1,y))) (0 if that vanishes), facing the camera.  Writes
+ * (overwrites) loss [3 n_views] (device) and the gradients of the summed
+ * losses: d_alpha, d_depth, d_dist [P] and d_normal (rgb layout).  All
+ * pointers non-NULL. */
+lv_status lv_aux_loss(lv_context* ctx, const lv_frame* frame, const float* depth,
+                      const float* alpha, const float* normal, const float* dist, float lam_tc,
+                      float lam_n, float lam_d, float* loss, float* d_alpha, float* d_depth,
+                      float* d_normal, float* d_dist, hipStream_t stream);
+
 /* Synchronises the stream and reports the number of (tile, voxel) pairs the
  * forward pass that filled `saved` produced: LV_OK if it fitted,
  * LV_ERR_CAPACITY otherwise. */

@@ -9,4 +9,5 @@ from .raster import (  # noqa: F401
     read_timings,
     guard_params, guard_workspace_size, prune_guard, split_params, split_workspace_size,
     footprint_range, subdivide_select, subdivide_apply,
+    forward_aux, backward_aux, aux_loss, RasterizeAuxFn, rasterize_aux,
 )

@@ -21,6 +21,16 @@
 // lanes that hold the same voxel in the same step (DPP, each 16-lane row a
 // 4 x 4 pixel block), then pre-reduced per chunk in LDS and flushed with one
 // global atomic add per (tile, voxel, component).
+//
+// Auxiliary channels (the AUX instances; the training objective's eq. 6 and
+// eq. 17 name the terms they serve without defining them): per pixel the
+// ray-space distortion sum_i sum_j w_i w_j |tm_i - tm_j| + 1/3 sum_i w_i^2 l_i
+// (tm chord midpoint, l chord length) and the rendered normal sum_k w_k n_k
+// with n_v = -u / |u|, u the gradient of the voxel's trilinear density at
+// the cell centre.  Front to back, the sum of the earlier weights is 1 - T
+// and their depth sum is the depth accumulated so far, so the distortion
+// takes one multiply-add chain per hit; the backward recovers the earlier
+// depth sum from the forward's depth.
 #include "lv_common.h"
 
 namespace lv {
@@ -44,6 +54,13 @@ struct Stage {
 struct Ray {
   float d[3];
   float inv[3];
+};
+
+// the voxel normal n = -u / |u| and 1 / |u| (0 when u = 0), for the AUX passes
+template <int CH>
+struct StageAux {
+  float n[3][CH];
+  float iu[CH];
 };
 
 // Error-free transformations (contraction is off, so these are evaluated as
@@ -95,11 +112,12 @@ __device__ __forceinline__ Ray pixel_ray(const lv_camera& c, int px, int py) {
   return r;
 }
 
-// Stage voxels [cb, cb + nc) of the tile list into LDS.
-template <int CH, int NT>
-__device__ __forceinline__ void stage_chunk(Stage<CH>& S, const RasterArgs& a, const uint32_t* ids,
-                                            uint32_t cb, uint32_t nc, int view,
-                                            const float o[3]) {
+// Stage voxels [cb, cb + nc) of the tile list into LDS (with AUX also the
+// voxel normals into SA).
+template <int CH, int NT, bool AUX>
+__device__ __forceinline__ void stage_chunk(Stage<CH>& S, StageAux<CH>* SA, const RasterArgs& a,
+                                            const uint32_t* ids, uint32_t cb, uint32_t nc,
+                                            int view, const float o[3]) {
   for (uint32_t k = threadIdx.x; k < uint32_t(CH); k += NT) {
     if (k < nc) {
       const uint32_t id = ids[cb + k];
@@ -126,6 +144,18 @@ __device__ __forceinline__ void stage_chunk(Stage<CH>& S, const RasterArgs& a, c
       S.cf[5][k] = (s101 - s100) - (s001 - s000);
       S.cf[6][k] = (s011 - s010) - (s001 - s000);
       S.cf[7][k] = ((s111 - s110) - (s101 - s100)) - ((s011 - s010) - (s001 - s000));
+      if (AUX) {
+        // u_a: a quarter of the summed corner differences along axis a
+        const float ux = 0.25f * (((s100 - s000) + (s110 - s010)) + ((s101 - s001) + (s111 - s011)));
+        const float uy = 0.25f * (((s010 - s000) + (s110 - s100)) + ((s011 - s001) + (s111 - s101)));
+        const float uz = 0.25f * (((s001 - s000) + (s101 - s100)) + ((s011 - s010) + (s111 - s110)));
+        const float ul = sqrtf(ux * ux + uy * uy + uz * uz);
+        const float iu = ul > 0.0f ? 1.0f / ul : 0.0f;
+        SA->n[0][k] = -ux * iu;
+        SA->n[1][k] = -uy * iu;
+        SA->n[2][k] = -uz * iu;
+        SA->iu[k] = iu;
+      }
       S.col[0][k] = __uint_as_float(r0.x);
       S.col[1][k] = __uint_as_float(r0.y);
       S.col[2][k] = __uint_as_float(r0.z);
@@ -270,7 +300,23 @@ __device__ __forceinline__ int pix_y_of_lane(int lane) { return (lane >> 5) * 4 
       LV_SEG_FMAC(K, 4) LV_SEG_FMAC(K, 5) LV_SEG_FMAC(K, 6) LV_SEG_FMAC(K, 7) LV_SEG_FMAC(K, 8) \
           LV_SEG_FMAC(K, 9) LV_SEG_FMAC(K, 10) "s_nop 1"
 
+#define LV_SEG_FMAC3(K, R) "v_fmac_f32_dpp %" #R ", %" #R ", %3 row_shr:" #K " row_mask:0xf bank_mask:0xf\n"
+#define LV_SEG_BLOCK3(K)                                                              \
+  "s_nop 1\n" LV_SEG_FMAC3(K, 0) LV_SEG_FMAC3(K, 1) LV_SEG_FMAC3(K, 2) "s_nop 1"
+
+// the same step over 3 further values (the normal gradient of the AUX pass)
 template <int K>
+__device__ __forceinline__ void seg_step3(float* v, float f) {
+#define LV_SEG_ASM3(K)                                                                           \
+  asm volatile(LV_SEG_BLOCK3(K) : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]) : "v"(f))
+  if constexpr (K == 1) LV_SEG_ASM3(1);
+  else if constexpr (K == 2) LV_SEG_ASM3(2);
+  else if constexpr (K == 4) LV_SEG_ASM3(4);
+  else LV_SEG_ASM3(8);
+#undef LV_SEG_ASM3
+}
+
+template <int K, int NV>
 __device__ __forceinline__ void seg_step(float* v, int dist) {
   if (__ballot(dist >= K) == 0) return;
   const float f = dist >= K ? 1.0f : 0.0f;
@@ -284,13 +330,17 @@ __device__ __forceinline__ void seg_step(float* v, int dist) {
   else if constexpr (K == 4) LV_SEG_ASM(4);
   else LV_SEG_ASM(8);
 #undef LV_SEG_ASM
+  if constexpr (NV > 11) seg_step3<K>(v + 11, f);
 }
 #undef LV_SEG_BLOCK
 #undef LV_SEG_FMAC
+#undef LV_SEG_BLOCK3
+#undef LV_SEG_FMAC3
 
 // After the call, a lane with `last` set holds in v the sum over its run of
 // lanes with the same key (pend lanes only; others form runs of their own).
-__device__ __forceinline__ bool seg_reduce_rows(float (&v)[11], int jj, bool pend) {
+template <int NV>
+__device__ __forceinline__ bool seg_reduce_rows(float (&v)[NV], int jj, bool pend) {
   const int lane = threadIdx.x & 63;
   const int key = pend ? jj : -1 - lane;
   const int prev = __builtin_amdgcn_update_dpp(0x7FFFFFFF, key, 0x111, 0xF, 0xF, false);
@@ -300,10 +350,10 @@ __device__ __forceinline__ bool seg_reduce_rows(float (&v)[11], int jj, bool pen
   if (H != ~0ull) {
     const unsigned long long le = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
     const int dist = lane - (63 - __builtin_clzll(H & le));
-    seg_step<1>(v, dist);
-    seg_step<2>(v, dist);
-    seg_step<4>(v, dist);
-    seg_step<8>(v, dist);
+    seg_step<1, NV>(v, dist);
+    seg_step<2, NV>(v, dist);
+    seg_step<4, NV>(v, dist);
+    seg_step<8, NV>(v, dist);
   }
   return last;
 }
@@ -339,17 +389,30 @@ __device__ __forceinline__ TileQueue tile_queue(uint32_t T, uint32_t* heads) {
 struct FwdState {
   float T, C0, C1, C2, D, Tpre;
   uint32_t nlast;
+  float N0, N1, N2, L;   // AUX: rendered normal, distortion
 };
 
 // one hit fragment (this lane's pixel, voxel jj at list position pos, chord
 // sg); returns w_k
-template <int CH>
-__device__ __forceinline__ float fwd_fragment(const Stage<CH>& S, int jj, uint32_t pos,
-                                              const Ray& ray, const Seg& sg, FwdState& st) {
+template <int CH, bool AUX>
+__device__ __forceinline__ float fwd_fragment(const Stage<CH>& S, const StageAux<CH>* SA, int jj,
+                                              uint32_t pos, const Ray& ray, const Seg& sg,
+                                              FwdState& st) {
   const Quad q = quad(S, jj, ray, sg);
   const float ex = __expf(-q.tau);
   const float al = opacity(q.tau, ex);
   const float wk = st.T * al;
+  if (AUX) {
+    // earlier weights sum to 1 - T and their depths to D: the pairs of this
+    // hit with the earlier ones add 2 wk (tm (1 - T) - D), its own segment
+    // wk^2 l / 3 with l = 2 hl
+    const float pair = fmaf(q.tm, 1.0f - st.T, -st.D);
+    st.L = fmaf(2.0f * wk, pair, st.L);
+    st.L = fmaf(wk * wk, q.hl * (2.0f / 3.0f), st.L);
+    st.N0 = fmaf(wk, SA->n[0][jj], st.N0);
+    st.N1 = fmaf(wk, SA->n[1][jj], st.N1);
+    st.N2 = fmaf(wk, SA->n[2][jj], st.N2);
+  }
   st.C0 = fmaf(wk, S.col[0][jj], st.C0);
   st.C1 = fmaf(wk, S.col[1][jj], st.C1);
   st.C2 = fmaf(wk, S.col[2][jj], st.C2);
@@ -360,12 +423,14 @@ __device__ __forceinline__ float fwd_fragment(const Stage<CH>& S, int jj, uint32
   return wk;
 }
 
-template <int TS, int NW>
+template <int TS, int NW, bool AUX>
 __global__ __launch_bounds__(TS* TS) void k_composite_fwd(RasterArgs a) {
   constexpr int NT = TS * TS;
   constexpr int CH = 64 * NW;
   constexpr int BPR = TS / 8;
   __shared__ Stage<CH> S;
+  __shared__ StageAux<AUX ? CH : 64> s_aux;
+  StageAux<CH>* SA = AUX ? reinterpret_cast<StageAux<CH>*>(&s_aux) : nullptr;
   __shared__ Masks<TS, CH> MK;
   __shared__ uint32_t s_wmax[CH];
   __shared__ uint32_t s_tile;
@@ -406,9 +471,10 @@ __global__ __launch_bounds__(TS* TS) void k_composite_fwd(RasterArgs a) {
     FwdState st;
     st.T = inimg ? 1.0f : 0.0f; st.C0 = st.C1 = st.C2 = 0.0f; st.D = 0.0f; st.Tpre = 1.0f;
     st.nlast = 0;
+    st.N0 = st.N1 = st.N2 = st.L = 0.0f;
     for (uint32_t cb = 0; cb < count; cb += CH) {
       const uint32_t nc = (count - cb) < uint32_t(CH) ? (count - cb) : uint32_t(CH);
-      stage_chunk<CH, NT>(S, a, ids, cb, nc, v, o);
+      stage_chunk<CH, NT, AUX>(S, SA, a, ids, cb, nc, v, o);
       for (int k = threadIdx.x; k < CH; k += NT) s_wmax[k] = 0u;
       __syncthreads();
       build_masks<TS, CH>(S, MK, nc, tx * TS, ty * TS);
@@ -423,7 +489,7 @@ __global__ __launch_bounds__(TS* TS) void k_composite_fwd(RasterArgs a) {
           m &= m - 1;
           const Seg sg = slab(S, jj, ray);
           if (sg.hit) {
-            const float wk = fwd_fragment(S, jj, cb + uint32_t(jj), ray, sg, st);
+            const float wk = fwd_fragment<CH, AUX>(S, SA, jj, cb + uint32_t(jj), ray, sg, st);
             if (wk > 0.0f) atomicMax(&s_wmax[jj], __float_as_uint(wk));
             if (st.T < a.t_eps) break;
           }
@@ -448,6 +514,15 @@ __global__ __launch_bounds__(TS* TS) void k_composite_fwd(RasterArgs a) {
       a.alpha[g] = 1.0f - st.T;
       a.ws.nlast[g] = st.nlast;
       a.ws.tpre[g] = st.Tpre;
+      if (AUX) {
+        if (a.dist) a.dist[g] = st.L;
+        if (a.normal) {
+          float* nm = a.normal + 3 * vt.pix_base + local;
+          nm[0] = st.N0;
+          nm[npv] = st.N1;
+          nm[2 * npv] = st.N2;
+        }
+      }
     }
   }
 }
@@ -472,16 +547,19 @@ struct BwdState {
   float gC0, gC1, gC2, gD, gA;
   float base, SC0, SC1, SC2, SD;
   bool first;
+  // AUX: upstream of the distortion and normal channels, the pixel's depth,
+  // suffix sums of w n, of w and of w times the distortion's dL/dw
+  float gL, Dt, gN0, gN1, gN2, SN0, SN1, SN2, SW, SG;
 };
 
 // Sequential part of one fragment (this lane's pixel, voxel jj), in the
 // pixel's back-to-front sweep: transmittance, weight and dL/dtau.  Returns
 // hit and, for a hit, what the deferred part needs: gh = dL/dtau * half
 // chord, the weight wk and the chord's midpoint and half length.
-template <int CH>
-__device__ __forceinline__ bool bwd_sweep(const Stage<CH>& S, int jj, const Ray& ray, BwdState& st,
-                                          const float bg[3], float& gh, float& wk, float& tm,
-                                          float& hl) {
+template <int CH, bool AUX>
+__device__ __forceinline__ bool bwd_sweep(const Stage<CH>& S, const StageAux<CH>* SA, int jj,
+                                          const Ray& ray, BwdState& st, const float bg[3],
+                                          float& gh, float& wk, float& tm, float& hl) {
   const Seg sg = slab(S, jj, ray);
   if (!sg.hit) return false;
   const Quad q = quad(S, jj, ray, sg);
@@ -503,6 +581,25 @@ __device__ __forceinline__ bool bwd_sweep(const Stage<CH>& S, int jj, const Ray&
   dtau = fmaf(st.gC0, Tafter * c0 - st.SC0, dtau);
   dtau = fmaf(st.gC1, Tafter * c1 - st.SC1, dtau);
   dtau = fmaf(st.gC2, Tafter * c2 - st.SC2, dtau);
+  if (AUX) {
+    // distortion: dL/dw_k = gL (2 (tm W - S) + 2 (S' - tm W') + (4/3) w_k hl), with
+    // W = 1 - T before the hit, S = D - w_k tm - S' the earlier sums, S' = SD
+    // and W' = SW the later ones
+    const float pre = fmaf(q.tm, 1.0f - Tbefore, -((st.Dt - wk * q.tm) - st.SD));
+    const float post = fmaf(-q.tm, st.SW, st.SD);
+    const float Gd = st.gL * (2.0f * (pre + post) + (4.0f / 3.0f) * wk * q.hl);
+    dtau += fmaf(Gd, Tafter, -st.SG);
+    st.SG = fmaf(wk, Gd, st.SG);
+    st.SW += wk;
+    // normal: like a colour without background
+    const float n0 = SA->n[0][jj], n1 = SA->n[1][jj], n2 = SA->n[2][jj];
+    dtau = fmaf(st.gN0, Tafter * n0 - st.SN0, dtau);
+    dtau = fmaf(st.gN1, Tafter * n1 - st.SN1, dtau);
+    dtau = fmaf(st.gN2, Tafter * n2 - st.SN2, dtau);
+    st.SN0 = fmaf(wk, n0, st.SN0);
+    st.SN1 = fmaf(wk, n1, st.SN1);
+    st.SN2 = fmaf(wk, n2, st.SN2);
+  }
   gh = dtau * q.hl;
   tm = q.tm;
   hl = q.hl;
@@ -521,7 +618,7 @@ __device__ __forceinline__ bool bwd_sweep(const Stage<CH>& S, int jj, const Ray&
 template <int CH>
 __device__ __forceinline__ void bwd_spread(const Stage<CH>& S, int jj, const float d[3], float gh,
                                            float wk, const float gc[3], float tm, float hl,
-                                           float g[11]) {
+                                           float* g) {
   const float ta = fmaf(-hl, kGL, tm), tb = fmaf(hl, kGL, tm);
   const float ie = S.inve[jj];
   float ua[3], ub[3];
@@ -557,27 +654,29 @@ __device__ __forceinline__ void bwd_spread(const Stage<CH>& S, int jj, const flo
 // fewer than kRing are ever pending).
 constexpr int kRing = 128;
 
-template <int CH>
+template <int CH, bool AUX>
 struct BwdRing {
   uint32_t key[kRing];   // jj | pixel lane << 16
   float gh[kRing], wk[kRing], tm[kRing], hl[kRing];
   float d[64][3];        // unit ray direction of each pixel of the wave
   float gc[64][3];       // dL/dC of each pixel of the wave
+  float gn[AUX ? 64 : 1][3];   // AUX: dL/dN of each pixel of the wave
 };
 
 // Processes the `count` (<= 64) oldest entries of the ring with one entry per
 // lane: corner and colour contributions, summed over runs of lanes on the
 // same voxel, added to the chunk's LDS accumulators.  Every lane of the
 // wave must call it.
-template <int CH>
-__device__ __forceinline__ void bwd_drain(const Stage<CH>& S, const BwdRing<CH>& R,
+template <int CH, bool AUX>
+__device__ __forceinline__ void bwd_drain(const Stage<CH>& S, const BwdRing<CH, AUX>& R,
                                           double (*s_g)[CH], uint32_t head, uint32_t count) {
+  constexpr int NV = AUX ? 14 : 11;
   const uint32_t lane = threadIdx.x & 63u;
   const bool valid = lane < count;
   int jj = 0;
-  float g[11];
+  float g[NV];
 #pragma unroll
-  for (int c = 0; c < 11; ++c) g[c] = 0.0f;
+  for (int c = 0; c < NV; ++c) g[c] = 0.0f;
   if (valid) {
     const uint32_t e = (head + lane) & uint32_t(kRing - 1);
     const uint32_t key = R.key[e];
@@ -586,27 +685,35 @@ __device__ __forceinline__ void bwd_drain(const Stage<CH>& S, const BwdRing<CH>&
     const float d[3] = {R.d[p][0], R.d[p][1], R.d[p][2]};
     const float gc[3] = {R.gc[p][0], R.gc[p][1], R.gc[p][2]};
     bwd_spread(S, jj, d, R.gh[e], R.wk[e], gc, R.tm[e], R.hl[e], g);
+    if (AUX) {   // dL/dn of the voxel: w times the pixel's dL/dN
+      g[11] = R.wk[e] * R.gn[p][0];
+      g[12] = R.wk[e] * R.gn[p][1];
+      g[13] = R.wk[e] * R.gn[p][2];
+    }
   }
-  const bool last = seg_reduce_rows(g, jj, valid);
+  const bool last = seg_reduce_rows<NV>(g, jj, valid);
   if (valid && last) {
 #pragma unroll
-    for (int c = 0; c < 11; ++c) atomicAdd(&s_g[c][jj], double(g[c]));
+    for (int c = 0; c < NV; ++c) atomicAdd(&s_g[c][jj], double(g[c]));
   }
 }
 
-template <int TS, int NW>
+template <int TS, int NW, bool AUX>
 __global__ __launch_bounds__(TS* TS) void k_composite_bwd(RasterArgs a) {
   constexpr int NT = TS * TS;
   constexpr int CH = 64 * NW;
   constexpr int BPR = TS / 8;
+  constexpr int NV = AUX ? 14 : 11;   // accumulated values per voxel
   __shared__ Stage<CH> S;
+  __shared__ StageAux<AUX ? CH : 64> s_aux;
+  StageAux<CH>* SA = AUX ? reinterpret_cast<StageAux<CH>*>(&s_aux) : nullptr;
   __shared__ Masks<TS, CH> MK;
-  __shared__ double s_g[11][CH];
-  __shared__ BwdRing<CH> s_ring[NT / 64];
+  __shared__ double s_g[NV][CH];
+  __shared__ BwdRing<CH, AUX> s_ring[NT / 64];
   __shared__ uint32_t s_tile, s_maxn;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lx = pix_x_of_lane(lane), ly = pix_y_of_lane(lane);
-  BwdRing<CH>& ring = s_ring[wave];
+  BwdRing<CH, AUX>& ring = s_ring[wave];
   const int wbx = (wave % BPR) * 8, wby = (wave / BPR) * 8;
   const float bg[3] = {a.bg[0], a.bg[1], a.bg[2]};
 
@@ -641,6 +748,8 @@ __global__ __launch_bounds__(TS* TS) void k_composite_bwd(RasterArgs a) {
     st.Tb = 1.0f; st.gC0 = st.gC1 = st.gC2 = st.gD = st.gA = 0.0f;
     st.base = st.SC0 = st.SC1 = st.SC2 = st.SD = 0.0f;
     st.first = true;
+    st.gL = st.Dt = st.gN0 = st.gN1 = st.gN2 = 0.0f;
+    st.SN0 = st.SN1 = st.SN2 = st.SW = st.SG = 0.0f;
     if (inimg) {
       const uint64_t local = uint64_t(py) * uint64_t(vt.W) + uint64_t(px);
       const uint64_t npv = uint64_t(vt.W) * uint64_t(vt.H);
@@ -651,10 +760,23 @@ __global__ __launch_bounds__(TS* TS) void k_composite_bwd(RasterArgs a) {
       st.gC0 = dr[0]; st.gC1 = dr[npv]; st.gC2 = dr[2 * npv];
       st.gD = a.d_depth ? a.d_depth[gp] : 0.0f;
       st.gA = a.d_alpha ? a.d_alpha[gp] : 0.0f;
+      if (AUX) {
+        if (a.d_dist) {
+          st.gL = a.d_dist[gp];
+          st.Dt = a.depth_fwd[gp];
+        }
+        if (a.d_normal) {
+          const float* dn = a.d_normal + 3 * vt.pix_base + local;
+          st.gN0 = dn[0]; st.gN1 = dn[npv]; st.gN2 = dn[2 * npv];
+        }
+      }
     }
     // the wave's rays and colour gradients, read back by the deferred part
     ring.d[lane][0] = ray.d[0]; ring.d[lane][1] = ray.d[1]; ring.d[lane][2] = ray.d[2];
     ring.gc[lane][0] = st.gC0; ring.gc[lane][1] = st.gC1; ring.gc[lane][2] = st.gC2;
+    if (AUX) {
+      ring.gn[lane][0] = st.gN0; ring.gn[lane][1] = st.gN1; ring.gn[lane][2] = st.gN2;
+    }
     if (nlast) atomicMax(&s_maxn, nlast);
     __syncthreads();
     const uint32_t maxn = s_maxn;
@@ -665,10 +787,10 @@ __global__ __launch_bounds__(TS* TS) void k_composite_bwd(RasterArgs a) {
     for (int ci = nch - 1; ci >= 0; --ci) {
       const uint32_t cb = uint32_t(ci) * CH;
       const uint32_t nc = (maxn - cb) < uint32_t(CH) ? (maxn - cb) : uint32_t(CH);
-      stage_chunk<CH, NT>(S, a, ids, cb, nc, v, o);
+      stage_chunk<CH, NT, AUX>(S, SA, a, ids, cb, nc, v, o);
       {
         double* z = &s_g[0][0];
-        for (int k = threadIdx.x; k < 11 * CH; k += NT) z[k] = 0.0;
+        for (int k = threadIdx.x; k < NV * CH; k += NT) z[k] = 0.0;
       }
       __syncthreads();
       build_masks<TS, CH>(S, MK, nc, tx * TS, ty * TS);
@@ -694,7 +816,7 @@ __global__ __launch_bounds__(TS* TS) void k_composite_bwd(RasterArgs a) {
             const int jbit = 63 - __builtin_clzll(m);
             m &= ~(1ull << jbit);
             jj = w * 64 + jbit;
-            hit = bwd_sweep(S, jj, ray, st, bg, gh, wk, tm, hl);
+            hit = bwd_sweep<CH, AUX>(S, SA, jj, ray, st, bg, gh, wk, tm, hl);
           }
           const unsigned long long hb = __ballot(hit);
           if (hb) {
@@ -723,11 +845,29 @@ __global__ __launch_bounds__(TS* TS) void k_composite_bwd(RasterArgs a) {
         rcount = 0u;
       }
       __syncthreads();
+      if (AUX) {
+        // the chunk's dL/dn of each voxel through n = -u / |u|: dL/du =
+        // -(g - (g . n) n) / |u|, and du_a/dsigma_c = +-1/4 (corner bit a)
+        for (uint32_t k = threadIdx.x; k < nc; k += NT) {
+          const double g0 = s_g[11][k], g1 = s_g[12][k], g2 = s_g[13][k];
+          const double n0 = SA->n[0][k], n1 = SA->n[1][k], n2 = SA->n[2][k];
+          const double gn = g0 * n0 + g1 * n1 + g2 * n2;
+          const double iu = SA->iu[k];
+          s_g[11][k] = -0.25 * (g0 - gn * n0) * iu;
+          s_g[12][k] = -0.25 * (g1 - gn * n1) * iu;
+          s_g[13][k] = -0.25 * (g2 - gn * n2) * iu;
+        }
+        __syncthreads();
+      }
       // flush: consecutive lanes take consecutive components of a voxel, so
       // its 8 density and 3 colour sums go out as two contiguous groups
       for (uint32_t e = threadIdx.x; e < 11u * nc; e += NT) {
         const uint32_t k = e / 11u, c = e - 11u * k;
-        const float s = float(s_g[c][k]);
+        double sd = s_g[c][k];
+        if (AUX && c < 8u)
+          sd += ((c & 1u) ? s_g[11][k] : -s_g[11][k]) + ((c & 2u) ? s_g[12][k] : -s_g[12][k]) +
+                ((c & 4u) ? s_g[13][k] : -s_g[13][k]);
+        const float s = float(sd);
         // colour gradients stop at the clamp (channels whose raw value <= 0)
         const bool pass = c < 8u || ((S.id[k] >> (kIdBits + (c - 8u))) & 1u);
         if (s != 0.0f && pass) {
@@ -757,44 +897,52 @@ static int persistent_grid(K kernel, int nt, uint32_t T, int grid_cap) {
   return int(g);
 }
 
-template <int TS, int NW>
+template <int TS, int NW, bool AUX>
 static hipError_t fwd_inst(const RasterArgs& a, int grid_cap, hipStream_t s) {
-  auto k = k_composite_fwd<TS, NW>;
+  auto k = k_composite_fwd<TS, NW, AUX>;
   const int g = persistent_grid(k, TS * TS, a.T, grid_cap);
   hipLaunchKernelGGL(k, dim3(g), dim3(TS * TS), 0, s, a);
   return hipGetLastError();
 }
 
-template <int TS, int NW>
+template <int TS, int NW, bool AUX>
 static hipError_t bwd_inst(const RasterArgs& a, int grid_cap, hipStream_t s) {
-  auto k = k_composite_bwd<TS, NW>;
+  auto k = k_composite_bwd<TS, NW, AUX>;
   const int g = persistent_grid(k, TS * TS, a.T, grid_cap);
   hipLaunchKernelGGL(k, dim3(g), dim3(TS * TS), 0, s, a);
   return hipGetLastError();
 }
 
-#define LV_DISPATCH(FN, a, chunk, cap, s)                              \
+#define LV_DISPATCH(FN, AUX, a, chunk, cap, s)                         \
   switch (a.TS * 1000 + chunk) {                                       \
-    case 8064: return FN<8, 1>(a, cap, s);                             \
-    case 8128: return FN<8, 2>(a, cap, s);                             \
-    case 8256: return FN<8, 4>(a, cap, s);                             \
-    case 16064: return FN<16, 1>(a, cap, s);                           \
-    case 16128: return FN<16, 2>(a, cap, s);                           \
-    case 16256: return FN<16, 4>(a, cap, s);                           \
-    case 32064: return FN<32, 1>(a, cap, s);                           \
-    case 32128: return FN<32, 2>(a, cap, s);                           \
-    case 32256: return FN<32, 4>(a, cap, s);                           \
+    case 8064: return FN<8, 1, AUX>(a, cap, s);                        \
+    case 8128: return FN<8, 2, AUX>(a, cap, s);                        \
+    case 8256: return FN<8, 4, AUX>(a, cap, s);                        \
+    case 16064: return FN<16, 1, AUX>(a, cap, s);                      \
+    case 16128: return FN<16, 2, AUX>(a, cap, s);                      \
+    case 16256: return FN<16, 4, AUX>(a, cap, s);                      \
+    case 32064: return FN<32, 1, AUX>(a, cap, s);                      \
+    case 32128: return FN<32, 2, AUX>(a, cap, s);                      \
+    case 32256: return FN<32, 4, AUX>(a, cap, s);                      \
     default: return hipErrorInvalidValue;                              \
   }
 
-hipError_t launch_composite_fwd(const RasterArgs& a, int chunk, int grid_cap, hipStream_t s) {
+hipError_t launch_composite_fwd(const RasterArgs& a, int chunk, int grid_cap, hipStream_t s,
+                                bool aux) {
   if (a.T == 0) return hipSuccess;
-  LV_DISPATCH(fwd_inst, a, chunk, grid_cap, s);
+  if (aux) {
+    LV_DISPATCH(fwd_inst, true, a, chunk, grid_cap, s);
+  }
+  LV_DISPATCH(fwd_inst, false, a, chunk, grid_cap, s);
 }
 
-hipError_t launch_composite_bwd(const RasterArgs& a, int chunk, int grid_cap, hipStream_t s) {
+hipError_t launch_composite_bwd(const RasterArgs& a, int chunk, int grid_cap, hipStream_t s,
+                                bool aux) {
   if (a.T == 0) return hipSuccess;
-  LV_DISPATCH(bwd_inst, a, chunk, grid_cap, s);
+  if (aux) {
+    LV_DISPATCH(bwd_inst, true, a, chunk, grid_cap, s);
+  }
+  LV_DISPATCH(bwd_inst, false, a, chunk, grid_cap, s);
 }
 
 }  // namespace lv

@@ -309,9 +309,30 @@ lv_status lv_query_sizes(lv_context* ctx, const lv_voxels* vox, const lv_frame* 
   return LV_OK;
 }
 
+static lv_status forward_impl(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
+                              const lv_settings* st, void* workspace, void* saved, float* rgb,
+                              float* depth, float* alpha, float* wmax, bool aux, float* dist,
+                              float* normal, hipStream_t stream);
+
 lv_status lv_forward(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
                      const lv_settings* st, void* workspace, void* saved, float* rgb, float* depth,
                      float* alpha, float* wmax, hipStream_t stream) {
+  return forward_impl(ctx, vox, frame, st, workspace, saved, rgb, depth, alpha, wmax, false,
+                      nullptr, nullptr, stream);
+}
+
+lv_status lv_forward_aux(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
+                         const lv_settings* st, void* workspace, void* saved, float* rgb,
+                         float* depth, float* alpha, float* wmax, float* dist, float* normal,
+                         hipStream_t stream) {
+  return forward_impl(ctx, vox, frame, st, workspace, saved, rgb, depth, alpha, wmax, true, dist,
+                      normal, stream);
+}
+
+static lv_status forward_impl(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
+                              const lv_settings* st, void* workspace, void* saved, float* rgb,
+                              float* depth, float* alpha, float* wmax, bool aux, float* dist,
+                              float* normal, hipStream_t stream) {
   if (!ctx) return LV_ERR_ARG;
   lv::Layout L;
   lv_status s = validate_all(ctx, vox, frame, st, &L);
@@ -327,6 +348,8 @@ lv_status lv_forward(lv_context* ctx, const lv_voxels* vox, const lv_frame* fram
   a.depth = depth;
   a.alpha = alpha;
   a.wmax = wmax;
+  a.dist = dist;
+  a.normal = normal;
   {
     PhaseTimer t(ctx, LV_PH_SETUP, stream);
     LV_TRY(lv::launch_setup(a, stream), "setup");   // also zeroes the tile counts
@@ -353,15 +376,43 @@ lv_status lv_forward(lv_context* ctx, const lv_voxels* vox, const lv_frame* fram
   }
   {
     PhaseTimer t(ctx, LV_PH_COMPOSITE_FWD, stream);
-    LV_TRY(lv::launch_composite_fwd(a, st->chunk, 0, stream), "composite forward");
+    LV_TRY(lv::launch_composite_fwd(a, st->chunk, 0, stream, aux), "composite forward");
   }
   return LV_OK;
 }
+
+static lv_status backward_impl(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
+                               const lv_settings* st, void* workspace, const void* saved,
+                               const float* d_rgb, const float* d_depth, const float* d_alpha,
+                               const float* depth_fwd, const float* d_dist,
+                               const float* d_normal, float* d_density, float* d_sh,
+                               hipStream_t stream);
 
 lv_status lv_backward(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
                       const lv_settings* st, void* workspace, const void* saved,
                       const float* d_rgb, const float* d_depth, const float* d_alpha,
                       float* d_density, float* d_sh, hipStream_t stream) {
+  return backward_impl(ctx, vox, frame, st, workspace, saved, d_rgb, d_depth, d_alpha, nullptr,
+                       nullptr, nullptr, d_density, d_sh, stream);
+}
+
+lv_status lv_backward_aux(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
+                          const lv_settings* st, void* workspace, const void* saved,
+                          const float* d_rgb, const float* d_depth, const float* d_alpha,
+                          const float* depth_fwd, const float* d_dist, const float* d_normal,
+                          float* d_density, float* d_sh, hipStream_t stream) {
+  if (ctx && d_dist && !depth_fwd)
+    return fail(ctx, LV_ERR_ARG, "d_dist needs depth_fwd (the depth of the forward pass)");
+  return backward_impl(ctx, vox, frame, st, workspace, saved, d_rgb, d_depth, d_alpha, depth_fwd,
+                       d_dist, d_normal, d_density, d_sh, stream);
+}
+
+static lv_status backward_impl(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
+                               const lv_settings* st, void* workspace, const void* saved,
+                               const float* d_rgb, const float* d_depth, const float* d_alpha,
+                               const float* depth_fwd, const float* d_dist,
+                               const float* d_normal, float* d_density, float* d_sh,
+                               hipStream_t stream) {
   if (!ctx) return LV_ERR_ARG;
   lv::Layout L;
   lv_status s = validate_all(ctx, vox, frame, st, &L);
@@ -379,13 +430,17 @@ lv_status lv_backward(lv_context* ctx, const lv_voxels* vox, const lv_frame* fra
   a.d_alpha = d_alpha;
   a.d_density = d_density;
   a.d_sh = d_sh;
+  a.d_dist = d_dist;
+  a.d_normal = d_normal;
+  a.depth_fwd = depth_fwd;
+  const bool aux = d_dist || d_normal;
   {
     PhaseTimer t(ctx, LV_PH_BWD_SETUP, stream);
     LV_TRY(lv::launch_bwd_setup(a, stream), "backward setup");
   }
   {
     PhaseTimer t(ctx, LV_PH_COMPOSITE_BWD, stream);
-    LV_TRY(lv::launch_composite_bwd(a, st->chunk_bwd ? st->chunk_bwd : st->chunk, 0, stream),
+    LV_TRY(lv::launch_composite_bwd(a, st->chunk_bwd ? st->chunk_bwd : st->chunk, 0, stream, aux),
            "composite backward");
   }
   {
@@ -545,6 +600,22 @@ lv_status lv_l1_grad(lv_context* ctx, const lv_frame* frame, const float* rgb, c
     return fail(ctx, LV_ERR_ARG, "rgb/target/weight/loss/d_rgb must be non-NULL");
   LV_TRY(lv::run_l1_grad(frame->cams_dev, frame->n_views, max_view_pixels(frame), rgb, target,
                          weight, loss, d_rgb, stream), "l1_grad");
+  return LV_OK;
+}
+
+lv_status lv_aux_loss(lv_context* ctx, const lv_frame* frame, const float* depth,
+                      const float* alpha, const float* normal, const float* dist, float lam_tc,
+                      float lam_n, float lam_d, float* loss, float* d_alpha, float* d_depth,
+                      float* d_normal, float* d_dist, hipStream_t stream) {
+  if (!ctx) return LV_ERR_ARG;
+  lv_status s = check_frame(ctx, frame);
+  if (s != LV_OK) return s;
+  if (!depth || !alpha || !normal || !dist || !loss || !d_alpha || !d_depth || !d_normal ||
+      !d_dist)
+    return fail(ctx, LV_ERR_ARG, "lv_aux_loss: every pointer must be non-NULL");
+  LV_TRY(lv::run_aux_loss(frame->cams_dev, frame->n_views, max_view_pixels(frame), depth, alpha,
+                          normal, dist, lam_tc, lam_n, lam_d, loss, d_alpha, d_depth, d_normal,
+                          d_dist, stream), "aux_loss");
   return LV_OK;
 }
 

@@ -238,6 +238,13 @@ struct RasterArgs {
   const float* d_rgb;
   const float* d_depth;
   const float* d_alpha;
+  // auxiliary channels (forward: written when non-null; backward: upstream
+  // gradients, each nullable, and the forward's depth, needed with d_dist)
+  float* dist;
+  float* normal;
+  const float* d_dist;
+  const float* d_normal;
+  const float* depth_fwd;
   float* d_density;
   float* d_sh;
 };
@@ -359,15 +366,21 @@ struct FillSet {   // word ranges filled by one launch
 };
 hipError_t launch_fill_set(const FillSet& f, hipStream_t s);
 hipError_t launch_preprocess(const RasterArgs& a, hipStream_t s);
+hipError_t run_aux_loss(const lv_camera* cams_dev, int V, uint64_t max_pix, const float* depth,
+                        const float* alpha, const float* normal, const float* dist, float lam_tc,
+                        float lam_n, float lam_d, float* loss, float* g_alpha, float* g_depth,
+                        float* g_normal, float* g_dist, hipStream_t s);
 hipError_t launch_count_records(const Rec* rec, uint64_t nrec, unsigned long long* out,
                                 hipStream_t s);
 hipError_t launch_scan_tiles(const RasterArgs& a, uint32_t nblk, hipStream_t s);
 hipError_t launch_emit(const RasterArgs& a, hipStream_t s);
 hipError_t launch_sort(const RasterArgs& a, hipStream_t s);
 hipError_t launch_order(const RasterArgs& a, hipStream_t s);
-hipError_t launch_composite_fwd(const RasterArgs& a, int chunk, int grid_cap, hipStream_t s);
+hipError_t launch_composite_fwd(const RasterArgs& a, int chunk, int grid_cap, hipStream_t s,
+                                bool aux = false);
 hipError_t launch_bwd_setup(const RasterArgs& a, hipStream_t s);
-hipError_t launch_composite_bwd(const RasterArgs& a, int chunk, int grid_cap, hipStream_t s);
+hipError_t launch_composite_bwd(const RasterArgs& a, int chunk, int grid_cap, hipStream_t s,
+                                bool aux = false);
 hipError_t launch_sh_bwd(const RasterArgs& a, hipStream_t s);
 
 }  // namespace lv

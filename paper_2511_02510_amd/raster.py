@@ -205,6 +205,34 @@ def backward(ctx, vox, frame, st, workspace, saved, d_rgb, d_depth, d_alpha, d_d
                                   _stream(stream)), "lv_backward")
 
 
+def forward_aux(ctx, vox, frame, st, workspace, saved, rgb, depth, alpha, wmax, dist, normal,
+                stream=None):
+    """lv_forward_aux: lv_forward plus the distortion [P] and normal [3P] channels."""
+    ctx.check(ctx.lib.lv_forward_aux(ctx.h, ctypes.byref(vox.struct), ctypes.byref(frame.struct),
+                                     ctypes.byref(st), _p(workspace), _p(saved), _p(rgb),
+                                     _p(depth), _p(alpha), _p(wmax), _p(dist), _p(normal),
+                                     _stream(stream)), "lv_forward_aux")
+
+
+def backward_aux(ctx, vox, frame, st, workspace, saved, d_rgb, d_depth, d_alpha, depth_fwd,
+                 d_dist, d_normal, d_density, d_sh, stream=None):
+    ctx.check(ctx.lib.lv_backward_aux(ctx.h, ctypes.byref(vox.struct), ctypes.byref(frame.struct),
+                                      ctypes.byref(st), _p(workspace), _p(saved), _p(d_rgb),
+                                      _p(d_depth), _p(d_alpha), _p(depth_fwd), _p(d_dist),
+                                      _p(d_normal), _p(d_density), _p(d_sh), _stream(stream)),
+              "lv_backward_aux")
+
+
+def aux_loss(ctx, frame, depth, alpha, normal, dist, lam_tc, lam_n, lam_d, loss, d_alpha,
+             d_depth, d_normal, d_dist, stream=None):
+    """lv_aux_loss: per-view transmittance-concentration, depth-normal and
+    distortion terms (loss [3 V]) and their gradients."""
+    ctx.check(ctx.lib.lv_aux_loss(ctx.h, ctypes.byref(frame.struct), _p(depth), _p(alpha),
+                                  _p(normal), _p(dist), float(lam_tc), float(lam_n), float(lam_d),
+                                  _p(loss), _p(d_alpha), _p(d_depth), _p(d_normal), _p(d_dist),
+                                  _stream(stream)), "lv_aux_loss")
+
+
 def check_overflow(ctx, vox, frame, st, saved, stream=None):
     """(fits, pairs_needed) of the forward pass that filled `saved`;
     synchronises the stream."""
@@ -491,9 +519,12 @@ class Renderer:
         return (torch.empty(3 * P, device=d), torch.empty(P, device=d), torch.empty(P, device=d))
 
     def forward(self, rgb, depth, alpha, wmax, vox: Optional[Voxels] = None, stream=None,
-                verify: Optional[bool] = None, saved: Optional[torch.Tensor] = None):
+                verify: Optional[bool] = None, saved: Optional[torch.Tensor] = None,
+                dist: Optional[torch.Tensor] = None, normal: Optional[torch.Tensor] = None):
         """Returns the saved-state buffer the pass wrote (`saved`, or a larger
-        replacement after a capacity re-plan; the renderer's own if None)."""
+        replacement after a capacity re-plan; the renderer's own if None).
+        With dist and/or normal the pass also renders those channels
+        (lv_forward_aux)."""
         vox = vox or self.vox
         own = saved is None
         saved = self.saved if own else saved
@@ -501,8 +532,17 @@ class Renderer:
         # a truncated pass composites without some occluders, so its weights
         # are not bounded by the true ones: keep w_max to restore on overflow
         keep = wmax.clone() if (verify and wmax is not None) else None
-        forward(self.ctx, vox, self.frame, self.st, self.workspace, saved, rgb, depth, alpha,
-                wmax, stream)
+        aux = dist is not None or normal is not None
+
+        def run(sv):
+            if aux:
+                forward_aux(self.ctx, vox, self.frame, self.st, self.workspace, sv, rgb, depth,
+                            alpha, wmax, dist, normal, stream)
+            else:
+                forward(self.ctx, vox, self.frame, self.st, self.workspace, sv, rgb, depth, alpha,
+                        wmax, stream)
+
+        run(saved)
         if verify:
             fits, need = check_overflow(self.ctx, vox, self.frame, self.st, saved, stream)
             self.checked = True
@@ -512,8 +552,7 @@ class Renderer:
                 self.st.pair_capacity = min(need + need // 8 + 4096, (1 << 32) - 1)
                 self._alloc()
                 saved = self.saved if own else self.new_saved()
-                forward(self.ctx, vox, self.frame, self.st, self.workspace, saved, rgb, depth,
-                        alpha, wmax, stream)
+                run(saved)
                 fits, need = check_overflow(self.ctx, vox, self.frame, self.st, saved, stream)
                 if not fits:
                     raise LiteVoxelError(_abi.LV_ERR_CAPACITY, f"{need} pairs do not fit")
@@ -530,6 +569,19 @@ class Renderer:
             raise LiteVoxelError(_abi.LV_ERR_ARG, "workspace smaller than the pass needs")
         backward(self.ctx, vox or self.vox, self.frame, st, self.workspace, saved, d_rgb, d_depth,
                  d_alpha, d_density, d_sh, stream)
+
+    def backward_aux(self, d_rgb, d_depth, d_alpha, depth_fwd, d_dist, d_normal, d_density, d_sh,
+                     vox: Optional[Voxels] = None, stream=None,
+                     saved: Optional[torch.Tensor] = None, st: Optional[LvSettings] = None):
+        """backward() with the upstream gradients of the distortion and normal
+        channels (lv_backward_aux); depth_fwd: the depth the pass rendered."""
+        st = st if st is not None else self.st
+        saved = self.saved if saved is None else saved
+        ws, _ = query_sizes(self.ctx, vox or self.vox, self.frame, st)
+        if ws > self.workspace.numel():
+            raise LiteVoxelError(_abi.LV_ERR_ARG, "workspace smaller than the pass needs")
+        backward_aux(self.ctx, vox or self.vox, self.frame, st, self.workspace, saved, d_rgb,
+                     d_depth, d_alpha, depth_fwd, d_dist, d_normal, d_density, d_sh, stream)
 
 
 class RasterizeFn(torch.autograd.Function):
@@ -574,3 +626,39 @@ class RasterizeFn(torch.autograd.Function):
 
 def rasterize(density, sh, renderer: Renderer, wmax: torch.Tensor):
     return RasterizeFn.apply(density, sh, renderer, wmax)
+
+
+class RasterizeAuxFn(torch.autograd.Function):
+    """RasterizeFn with the auxiliary channels: (density, sh) -> (rgb [3P],
+    depth [P], alpha [P], dist [P], normal [3P]).  The node keeps the pass's
+    saved state and its depth (the backward of the distortion reads it)."""
+
+    @staticmethod
+    def forward(ctx, density, sh, renderer: Renderer, wmax: torch.Tensor):
+        vox = renderer.vox.with_params(density.detach().contiguous(), sh.detach().contiguous())
+        rgb, depth, alpha = renderer.new_outputs()
+        P = renderer.frame.P
+        dist = torch.empty(P, device=rgb.device)
+        normal = torch.empty(3 * P, device=rgb.device)
+        saved = renderer.forward(rgb, depth, alpha, wmax, vox=vox, saved=renderer.new_saved(),
+                                 dist=dist, normal=normal)
+        ctx.renderer, ctx.vox, ctx.saved_state = renderer, vox, saved
+        ctx.st = renderer.settings_copy()
+        ctx.depth = depth.detach().clone()
+        ctx.mark_non_differentiable(wmax)
+        return rgb, depth, alpha, dist, normal
+
+    @staticmethod
+    def backward(ctx, g_rgb, g_depth, g_alpha, g_dist, g_normal):
+        r, vox = ctx.renderer, ctx.vox
+        d_density = torch.empty_like(vox.density)
+        d_sh = torch.empty_like(vox.sh)
+        c = lambda g: g.contiguous() if g is not None else None
+        g_rgb = c(g_rgb) if g_rgb is not None else torch.zeros(3 * r.frame.P, device=vox.density.device)
+        r.backward_aux(g_rgb, c(g_depth), c(g_alpha), ctx.depth, c(g_dist), c(g_normal), d_density,
+                       d_sh, vox=vox, saved=ctx.saved_state, st=ctx.st)
+        return d_density, d_sh, None, None
+
+
+def rasterize_aux(density, sh, renderer: Renderer, wmax: torch.Tensor):
+    return RasterizeAuxFn.apply(density, sh, renderer, wmax)

@@ -1,0 +1,201 @@
+"""GPU parity of the auxiliary render channels and terms (eq. 6 and 17 name
+them; readings in include/litevoxel.h and oracle/): the distortion and normal
+channels of lv_forward_aux, the adjoint of lv_backward_aux, the image terms of
+lv_aux_loss, and the whole chain channels -> terms -> gradient, against the
+FP64 oracle on the same seeded inputs, through the C-ABI."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import aux as oaux
+from synth.scenes import look_at
+from gpu_helpers import GRAD_TOL, IMG_TOL, WMAX_TOL, check_images, rel_l2, say, small_shell, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2511_02510_amd as lv
+    c = lv.Context(0)
+    yield c
+    c.close()
+
+
+def _scene():
+    sc = small_shell(20000, seed=81, deg=2, lmin=4, lmax=9, clutter=0.1)
+    cams = [look_at((2.0, 0.7, 1.3), 96, 72), look_at((-1.3, 0.6, -2.1), 80, 60),
+            look_at((0.4, -2.2, 1.1), 67, 53)]
+    return sc, cams
+
+
+def _render(ctx, sc, cams, tile=16, chunk=64, chunk_bwd=0):
+    import torch
+    import paper_2511_02510_amd as lv
+    dev = ctx.device
+    vox = lv.Voxels.from_scene(sc, dev)
+    frame = lv.Frame(cams, dev)
+    r = lv.Renderer(ctx, vox, frame, lv.settings(tile=tile, chunk=chunk, chunk_bwd=chunk_bwd))
+    rgb, depth, alpha = r.new_outputs()
+    P = frame.P
+    dist, normal = torch.empty(P, device=dev), torch.empty(3 * P, device=dev)
+    wmax = torch.zeros(vox.n, device=dev)
+    r.forward(rgb, depth, alpha, wmax, dist=dist, normal=normal)
+    torch.cuda.synchronize()
+    return r, vox, frame, dict(rgb=rgb, depth=depth, alpha=alpha, dist=dist, normal=normal,
+                               wmax=wmax)
+
+
+def _np(t):
+    return t.cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("tile,chunk", [(16, 64), (8, 256), (32, 128)])
+def test_aux_channels_forward(ctx, tile, chunk):
+    import torch
+    sc, cams = _scene()
+    say(f"aux forward: {sc.n} voxels, 3 views, tile {tile} chunk {chunk}")
+    r, vox, frame, out = _render(ctx, sc, cams, tile, chunk)
+    ref = oracle.render_aux(sc, cams)
+    got = {k: _np(v) for k, v in out.items()}
+    check_images(got, ref)
+    e_w = float(np.abs(got["wmax"] - ref["wmax"]).max())
+    e_l = float(np.abs(got["dist"] - ref["dist"]).max())
+    e_n = float(np.abs(got["normal"] - ref["normal"]).max())
+    say(f"  w_max {e_w:.2e}  dist {e_l:.2e} (max {ref['dist'].max():.3e})  normal {e_n:.2e}")
+    assert e_w <= WMAX_TOL and e_l <= IMG_TOL and e_n <= IMG_TOL
+    assert ref["dist"].max() > 1e-3 and np.abs(ref["normal"]).max() > 0.3
+    # the plain channels are the plain forward's, bit for bit
+    rgb, depth, alpha = r.new_outputs()
+    wm = torch.zeros(vox.n, device=ctx.device)
+    r.forward(rgb, depth, alpha, wm)
+    torch.cuda.synchronize()
+    for k, t in (("rgb", rgb), ("depth", depth), ("alpha", alpha), ("wmax", wm)):
+        assert torch.equal(t, out[k]), k
+
+
+@pytest.mark.parametrize("which", ["all", "dist", "normal"])
+def test_aux_backward_matches_oracle(ctx, which):
+    import torch
+    sc, cams = _scene()
+    r, vox, frame, out = _render(ctx, sc, cams, 16, 64)
+    P = frame.P
+    rng = np.random.default_rng(82)
+    g_rgb = rng.normal(0, 1e-3, 3 * P)
+    g_depth = rng.normal(0, 1e-4, P)
+    g_alpha = rng.normal(0, 1e-3, P)
+    g_dist = rng.normal(0, 1e-2, P) if which in ("all", "dist") else None
+    g_normal = rng.normal(0, 1e-3, 3 * P) if which in ("all", "normal") else None
+    dev = ctx.device
+    dd, dsh = torch.empty_like(vox.density), torch.empty_like(vox.sh)
+    t = lambda a: None if a is None else to_dev(a, dev)
+    r.backward_aux(t(g_rgb), t(g_depth), t(g_alpha), out["depth"], t(g_dist), t(g_normal), dd, dsh)
+    torch.cuda.synchronize()
+    dd_ref, dsh_ref = oracle.backward_aux(sc, cams, g_rgb, g_depth, g_alpha, g_dist, g_normal)
+    e = rel_l2(np.concatenate([_np(dd).ravel(), _np(dsh).ravel()]),
+               np.concatenate([dd_ref.ravel(), dsh_ref.ravel()]))
+    # the auxiliary part alone
+    dd0, dsh0 = oracle.backward(sc, cams, g_rgb, g_depth, g_alpha)
+    e_aux = rel_l2(_np(dd) - dd0, dd_ref - dd0)
+    say(f"  aux backward [{which}]: gradient rel-L2 {e:.2e}, density part of the aux terms {e_aux:.2e}")
+    assert e <= GRAD_TOL and e_aux <= GRAD_TOL
+
+
+def test_aux_loss_kernel_matches_oracle(ctx):
+    import torch
+    import paper_2511_02510_amd as lv
+    cams = [look_at((0.3, 0.4, -2.5), 64, 48), look_at((2.0, 0.1, 0.5), 37, 29),
+            look_at((1.0, 1.0, 1.0), 2, 9)]
+    frame = lv.Frame(cams, ctx.device)
+    P = frame.P
+    rng = np.random.default_rng(83)
+    depth = np.concatenate([
+        (2.5 + 0.3 * np.sin(np.arange(c.npix) * 0.01) + rng.normal(0, 0.01, c.npix)) for c in cams])
+    alpha = rng.uniform(0, 1, P)
+    normal = rng.normal(0, 0.4, 3 * P)
+    dist = rng.uniform(0, 0.05, P)
+    lam = (0.3, 0.7, 1.9)
+    L_ref, ga, gd, gn, gl = oaux.aux_losses(depth, alpha, normal, dist, cams, *lam)
+    dev = ctx.device
+    f32 = lambda a: to_dev(a, dev)
+    loss = torch.full((3 * len(cams),), 7.0, device=dev)
+    bufs = [torch.full((P,), 9.0, device=dev), torch.full((P,), 9.0, device=dev),
+            torch.full((3 * P,), 9.0, device=dev), torch.full((P,), 9.0, device=dev)]
+    lv.aux_loss(ctx, frame, f32(depth), f32(alpha), f32(normal), f32(dist), *lam, loss, *bufs)
+    torch.cuda.synchronize()
+    Lg = _np(loss).reshape(len(cams), 3)
+    say(f"  aux losses GPU {Lg.ravel()} oracle {L_ref.ravel()}")
+    assert np.allclose(Lg, L_ref, rtol=1e-4, atol=1e-7)
+    for name, g, ref in (("alpha", bufs[0], ga), ("depth", bufs[1], gd), ("normal", bufs[2], gn),
+                         ("dist", bufs[3], gl)):
+        e = rel_l2(_np(g), ref)
+        say(f"  d_{name} rel-L2 {e:.2e}")
+        assert e <= 1e-4, name
+
+
+def test_aux_chain_loss_and_gradient(ctx):
+    """channels -> image terms -> gradient, the whole chain on both sides."""
+    import torch
+    import paper_2511_02510_amd as lv
+    sc, cams = _scene()
+    r, vox, frame, out = _render(ctx, sc, cams, 16, 64)
+    lam = (0.05, 0.2, 5.0)
+    dev, P = ctx.device, frame.P
+    loss = torch.empty(3 * len(cams), device=dev)
+    ga, gd, gl = (torch.empty(P, device=dev) for _ in range(3))
+    gn = torch.empty(3 * P, device=dev)
+    lv.aux_loss(ctx, frame, out["depth"], out["alpha"], out["normal"], out["dist"], *lam, loss, ga,
+                gd, gn, gl)
+    dd, dsh = torch.empty_like(vox.density), torch.empty_like(vox.sh)
+    zero_rgb = torch.zeros(3 * P, device=dev)
+    r.backward_aux(zero_rgb, gd, ga, out["depth"], gl, gn, dd, dsh)
+    torch.cuda.synchronize()
+    ref = oracle.render_aux(sc, cams)
+    L_ref, ga_r, gd_r, gn_r, gl_r = oaux.aux_losses(ref["depth"], ref["alpha"], ref["normal"],
+                                                    ref["dist"], cams, *lam)
+    dd_r, dsh_r = oracle.backward_aux(sc, cams, np.zeros(3 * P), gd_r, ga_r, gl_r, gn_r)
+    Lg = _np(loss).reshape(len(cams), 3)
+    say(f"  chain losses GPU {Lg.ravel()} oracle {L_ref.ravel()}")
+    assert np.allclose(Lg, L_ref, rtol=1e-3, atol=1e-6)
+    e = rel_l2(_np(dd), dd_r)
+    say(f"  chain gradient rel-L2 {e:.2e}")
+    assert e <= GRAD_TOL
+    assert np.all(_np(dsh) == 0.0)    # no colour term in this loss
+
+
+def test_aux_autograd_matches_direct_calls(ctx):
+    import torch
+    import paper_2511_02510_amd as lv
+    sc, cams = _scene()
+    dev = ctx.device
+    vox = lv.Voxels.from_scene(sc, dev)
+    frame = lv.Frame(cams, dev)
+    r = lv.Renderer(ctx, vox, frame, lv.settings(tile=16, chunk=64))
+    dens = vox.density.clone().requires_grad_(True)
+    sh = vox.sh.clone().requires_grad_(True)
+    wmax = torch.zeros(vox.n, device=dev)
+    rgb, depth, alpha, dist, normal = lv.rasterize_aux(dens, sh, r, wmax)
+    rng = np.random.default_rng(84)
+    P = frame.P
+    w = [to_dev(rng.normal(0, s, n), dev) for s, n in ((1e-3, 3 * P), (1e-4, P), (1e-3, P),
+                                                       (1e-2, P), (1e-3, 3 * P))]
+    L = sum((o * wi).sum() for o, wi in zip((rgb, depth, alpha, dist, normal), w))
+    L.backward()
+    torch.cuda.synchronize()
+    dd_ref, dsh_ref = oracle.backward_aux(sc, cams, *[_np(x) for x in w])
+    e = rel_l2(np.concatenate([_np(dens.grad).ravel(), _np(sh.grad).ravel()]),
+               np.concatenate([dd_ref.ravel(), dsh_ref.ravel()]))
+    say(f"  autograd aux gradient rel-L2 {e:.2e}")
+    assert e <= GRAD_TOL
+
+
+def test_aux_argument_errors(ctx):
+    import torch
+    import paper_2511_02510_amd as lv
+    sc, cams = _scene()
+    r, vox, frame, out = _render(ctx, sc, cams, 16, 64)
+    P = frame.P
+    dd, dsh = torch.empty_like(vox.density), torch.empty_like(vox.sh)
+    g = torch.zeros(P, device=ctx.device)
+    with pytest.raises(lv.LiteVoxelError):   # d_dist without the forward's depth
+        r.backward_aux(torch.zeros(3 * P, device=ctx.device), None, None, None, g, None, dd, dsh)
