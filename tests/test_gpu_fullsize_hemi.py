@@ -2,9 +2,11 @@
 SH3, 16 views of 1920x1080 on a hemisphere (33.2 MP), with the depth-binned
 w_max quantile (16 bins, q = 0.1) on device.  The oracle computes what it can
 one by one: every record's key and every tile list (bit-exact), a seeded
-sample of pixels, w_max of a sample of voxels (over every pixel their
-footprint covers), the gradient of a loss that lives on the sampled pixels,
-and the bins, cutoffs and prune mask from the GPU's own w_max (bit-exact)."""
+sample of pixels, every pixel of two whole views (each view's image depends
+on that view only), w_max of a sample of voxels (over every pixel their
+footprint covers), the gradient of a loss that lives on the sampled pixels
+and of one on every pixel of the two views, and the bins, cutoffs and prune
+mask from the GPU's own w_max (bit-exact)."""
 import numpy as np
 import pytest
 
@@ -16,6 +18,7 @@ from gpu_helpers import GRAD_TOL, IMG_TOL, WMAX_TOL, rel_l2, rgb_index, say, to_
 pytestmark = pytest.mark.gpu
 
 TILE, CHUNK = 16, 128
+WHOLE = (3, 11)   # views compared pixel by pixel
 
 
 @pytest.fixture(scope="module")
@@ -51,6 +54,17 @@ def hemi():
     prune = torch.empty(vox.n, dtype=torch.uint8, device=dev)
     bins = torch.empty(vox.n, dtype=torch.uint8, device=dev)
     lv.depth_quantile(ctx, vox, frame, wmax, nb, 0.1, ws, tau, prune, bins)
+    # a loss on every pixel of the two whole views
+    off = oracle.pix_offsets(cams)
+    w_rgb, w_depth = np.zeros(3 * P), np.zeros(P)
+    for v in WHOLE:
+        n = int(off[v + 1] - off[v])
+        w_rgb[3 * int(off[v]):3 * int(off[v + 1])] = rng.normal(0, 1e-3, 3 * n)
+        w_depth[int(off[v]):int(off[v + 1])] = rng.normal(0, 1e-4, n)
+    ddw = torch.empty_like(vox.density)
+    dshw = torch.empty_like(vox.sh)
+    say("  backward of a loss on two whole views")
+    r.backward(to_dev(w_rgb, dev), to_dev(w_depth, dev), None, ddw, dshw)
     torch.cuda.synchronize()
     say("  exporting the tile lists")
     out = dict(scene=scene, cams=cams, pix=pix, grads=(g_rgb, g_depth, g_alpha),
@@ -58,6 +72,8 @@ def hemi():
                alpha=alpha.cpu().numpy().astype(np.float64), wmax=wmax.cpu().numpy(),
                dd=dd.cpu().numpy().astype(np.float64), dsh=dsh.cpu().numpy().astype(np.float64),
                bins=bins.cpu().numpy(), tau=tau.cpu().numpy(), prune=prune.cpu().numpy(),
+               wgrads=(w_rgb, w_depth), ddw=ddw.cpu().numpy().astype(np.float64),
+               dshw=dshw.cpu().numpy().astype(np.float64),
                tiles=lv.export_bins(ctx, vox, frame, r.st, r.saved))
     del r, vox, frame
     ctx.close()
@@ -88,6 +104,37 @@ def test_hemi_sampled_pixels(hemi):
     e_a = np.abs(hemi["alpha"][pix] - ref["alpha"][pix]).max()
     say(f"  max abs: rgb {e_rgb:.2e} depth {e_d:.2e} alpha {e_a:.2e}")
     assert e_rgb <= IMG_TOL and e_d <= IMG_TOL and e_a <= IMG_TOL
+
+
+def _views(hemi, flat3, flat1):
+    """The two whole views' rgb and depth/alpha slices of full-frame arrays."""
+    off = oracle.pix_offsets(hemi["cams"])
+    rgb = np.concatenate([flat3[3 * int(off[v]):3 * int(off[v + 1])] for v in WHOLE])
+    one = [np.concatenate([a[int(off[v]):int(off[v + 1])] for v in WHOLE]) for a in flat1]
+    return rgb, one
+
+
+def test_hemi_two_whole_views_every_pixel(hemi):
+    say(f"hemisphere: every pixel of views {WHOLE} (2 x 1920 x 1080)")
+    sub = [hemi["cams"][v] for v in WHOLE]
+    ref = oracle.render(hemi["scene"], sub)
+    rgb, (depth, alpha) = _views(hemi, hemi["rgb"], (hemi["depth"], hemi["alpha"]))
+    e_rgb = np.abs(rgb - ref["rgb"]).max()
+    e_d = np.abs(depth - ref["depth"]).max()
+    e_a = np.abs(alpha - ref["alpha"]).max()
+    say(f"  max abs: rgb {e_rgb:.2e} depth {e_d:.2e} alpha {e_a:.2e}")
+    assert e_rgb <= IMG_TOL and e_d <= IMG_TOL and e_a <= IMG_TOL
+    assert np.count_nonzero(ref["alpha"]) > 100000
+
+
+def test_hemi_two_whole_views_gradient(hemi):
+    say(f"hemisphere: gradient of a loss on every pixel of views {WHOLE}")
+    sub = [hemi["cams"][v] for v in WHOLE]
+    g_rgb, (g_depth,) = _views(hemi, hemi["wgrads"][0], (hemi["wgrads"][1],))
+    dd, dsh = oracle.backward(hemi["scene"], sub, g_rgb, g_depth)
+    e1, e2 = rel_l2(hemi["ddw"], dd), rel_l2(hemi["dshw"], dsh)
+    say(f"  rel L2: density {e1:.2e} sh {e2:.2e}")
+    assert e1 <= GRAD_TOL and e2 <= GRAD_TOL
 
 
 def test_hemi_sampled_wmax(hemi):
