@@ -482,6 +482,56 @@ def main():
            "apply_hbm_frac": round(per_voxel * (scene.n + n_out) / (t_apply * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     log(f"[bench] subdivision {subdiv}")
 
+    # ---- the auxiliary channels and terms on this workload: forward with the
+    # distortion and normal channels, loss weight, L1, the three auxiliary
+    # terms, one backward taking every channel's gradient
+    dist_c, normal_c = torch.empty(P, device=dev), torch.empty(3 * P, device=dev)
+    aloss = torch.empty(3 * len(cams), device=dev)
+    ga_c, gd_c, gl_c = (torch.empty(P, device=dev) for _ in range(3))
+    gn_c = torch.empty(3 * P, device=dev)
+
+    def aux_step(verify=False):
+        lv.lf_weight(ctx, frame, target, gamma, 0, 1e-3, weight, lw_ws, stream=stream)
+        r.forward(rgb, depth, alpha, wmax, stream=stream, verify=verify, dist=dist_c,
+                  normal=normal_c)
+        lv.l1_grad(ctx, frame, rgb, target, weight, loss, d_rgb, stream=stream)
+        lv.aux_loss(ctx, frame, depth, alpha, normal_c, dist_c, 0.01, 0.05, 1.0, aloss, ga_c,
+                    gd_c, gn_c, gl_c, stream=stream)
+        r.backward_aux(d_rgb, gd_c, ga_c, depth, gl_c, gn_c, d_density, d_sh, stream=stream)
+
+    aux_step(verify=True)
+    torch.cuda.synchronize()
+    lv.set_timing(ctx, True)
+    lv.read_timings(ctx)
+    for _ in range(max(3, args.steps // 2)):
+        aux_step()
+    aph = lv.read_timings(ctx)
+    lv.set_timing(ctx, False)
+    aphases = {k: (ms / max(c, 1)) for k, (ms, c) in aph.items()}
+    t_aux_loss = gpu_ms(lambda: lv.aux_loss(ctx, frame, depth, alpha, normal_c, dist_c, 0.01, 0.05,
+                                            1.0, aloss, ga_c, gd_c, gn_c, gl_c, stream=stream),
+                        max(5, args.steps // 2))
+    lv.graph_begin(ctx, stream)
+    aux_step()
+    lv.graph_end(ctx, stream)
+    for _ in range(args.warmup):
+        lv.graph_launch(ctx, stream)
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    for _ in range(args.steps):
+        lv.graph_launch(ctx, stream)
+    torch.cuda.synchronize()
+    aux_ms = 1e3 * (time.perf_counter() - ta) / args.steps
+    lv.graph_reset(ctx)
+    aux = {"step": "fwd (+ distortion, normal) + lf_weight + l1 + aux terms + bwd (all channels)",
+           "ms_per_step": round(aux_ms, 4), "mp_s": round(P / aux_ms / 1e3, 2),
+           "composite_fwd_ms": round(aphases["composite_fwd"], 4),
+           "composite_bwd_ms": round(aphases["composite_bwd"], 4),
+           "aux_loss_ms": round(t_aux_loss, 4),
+           "plain_composite_fwd_ms": round(phases["composite_fwd"], 4),
+           "plain_composite_bwd_ms": round(phases["composite_bwd"], 4)}
+    log(f"[bench] auxiliary channels and terms {aux}")
+
     # ---- the other workloads
     others = {}
     for name in [w for w in args.other_workloads.split(",") if w]:
@@ -550,7 +600,7 @@ def main():
         "phases_ms": {k: round(v, 4) for k, v in phases.items()},
         "whole_path_hbm": hbm,
         "other_workloads": others,
-        "next_rows": {"prune_guard": guard, "subdivide": subdiv},
+        "next_rows": {"prune_guard": guard, "subdivide": subdiv, "aux_terms": aux},
     }
     print(json.dumps(out), flush=True)
     ctx.close()

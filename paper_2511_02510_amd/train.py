@@ -4,7 +4,11 @@ and its gamma ramp (eq. 7-10, eq. 9), Adam on the corner densities and SH
 coefficients, and every `adapt_every` steps the depth-aware pruning with its
 stability guards (Sec. IV-C) followed by priority-driven subdivision
 (Sec. IV-D), after which the optimizer is refreshed (its state is reset, as
-the topology changed).
+the topology changed).  Optional weights lam_tc, lam_n, lam_d add the
+transmittance-concentration, depth-normal-consistency and distortion terms
+that eq. 6 and eq. 17 name (the library's readings of them) to the objective:
+the pass then renders the distortion and normal channels as well, and their
+gradients join the photometric one in a single backward.
 
 Every per-pixel and per-voxel step of the method is a library call; PyTorch
 holds the tensors, runs Adam and gathers the kept voxels.  A global-threshold
@@ -46,6 +50,13 @@ class TrainConfig:
     split: Dict[str, float] = dataclasses.field(default_factory=dict)
     tile: int = 16
     chunk: int = 64
+    lam_tc: float = 0.0             # transmittance concentration
+    lam_n: float = 0.0              # depth-normal consistency
+    lam_d: float = 0.0              # ray-space distortion
+
+    @property
+    def aux(self) -> bool:
+        return self.lam_tc != 0.0 or self.lam_n != 0.0 or self.lam_d != 0.0
 
 
 def psnr(rgb: torch.Tensor, target: torch.Tensor) -> float:
@@ -67,6 +78,13 @@ class Trainer:
                                  device=self.dev)
         self.loss = torch.empty(frame.n_views, device=self.dev)
         self.d_rgb = torch.empty(3 * P, device=self.dev)
+        if cfg.aux:
+            self.dist = torch.empty(P, device=self.dev)
+            self.normal = torch.empty(3 * P, device=self.dev)
+            self.aux_loss = torch.empty(3 * frame.n_views, device=self.dev)
+            self.g_alpha, self.g_depth, self.g_dist = (torch.empty(P, device=self.dev)
+                                                       for _ in range(3))
+            self.g_normal = torch.empty(3 * P, device=self.dev)
         self.gamma = None
         self._set_voxels(vox, torch.ones(vox.n, device=self.dev),
                          torch.ones(vox.n, dtype=torch.uint8, device=self.dev))
@@ -94,17 +112,35 @@ class Trainer:
             lv.lf_weight(self.ctx, self.frame, self.target, gamma, c.form, c.eps, self.weight,
                          self.lw_ws)
             self.gamma = gamma
-        self.renderer.forward(self.rgb, self.depth, self.alpha, self.wmax)
-        lv.l1_grad(self.ctx, self.frame, self.rgb, self.target, self.weight, self.loss, self.d_rgb)
         gd = torch.empty_like(self.density)
         gs = torch.empty_like(self.sh)
-        self.renderer.backward(self.d_rgb, None, None, gd, gs)
+        if c.aux:
+            self.renderer.forward(self.rgb, self.depth, self.alpha, self.wmax, dist=self.dist,
+                                  normal=self.normal)
+            lv.l1_grad(self.ctx, self.frame, self.rgb, self.target, self.weight, self.loss,
+                       self.d_rgb)
+            lv.aux_loss(self.ctx, self.frame, self.depth, self.alpha, self.normal, self.dist,
+                        c.lam_tc, c.lam_n, c.lam_d, self.aux_loss, self.g_alpha, self.g_depth,
+                        self.g_normal, self.g_dist)
+            # channels whose term has zero weight get no gradient pass
+            self.renderer.backward_aux(
+                self.d_rgb, self.g_depth if c.lam_n else None,
+                self.g_alpha if (c.lam_tc or c.lam_n) else None, self.depth,
+                self.g_dist if c.lam_d else None, self.g_normal if c.lam_n else None, gd, gs)
+        else:
+            self.renderer.forward(self.rgb, self.depth, self.alpha, self.wmax)
+            lv.l1_grad(self.ctx, self.frame, self.rgb, self.target, self.weight, self.loss,
+                       self.d_rgb)
+            self.renderer.backward(self.d_rgb, None, None, gd, gs)
         self.useful.add_(gd.abs().sum(dim=0))      # usefulness: gradient mass over the window
         self.density.grad, self.sh.grad = gd, gs
         self.opt.step()
 
     def loss_value(self) -> float:
-        return float(self.loss.sum())   # of the last step (synchronises)
+        """Total objective of the last step (synchronises)."""
+        if self.cfg.aux:
+            return float(self.loss.sum() + self.aux_loss.sum())
+        return float(self.loss.sum())
 
     # ------------------------------------------------------------ adaptation
     def adapt(self) -> dict:

@@ -29,12 +29,12 @@ def _scene():
     return sc, cams
 
 
-def _render(ctx, sc, cams, tile=16, chunk=64, chunk_bwd=0):
+def _render(ctx, sc, cams, tile=16, chunk=64, chunk_bwd=0, vox=None, bg=(0.0, 0.0, 0.0)):
     import torch
     import paper_2511_02510_amd as lv
     dev = ctx.device
-    vox = lv.Voxels.from_scene(sc, dev)
-    frame = lv.Frame(cams, dev)
+    vox = lv.Voxels.from_scene(sc, dev) if vox is None else vox
+    frame = lv.Frame(cams, dev, bg=bg)
     r = lv.Renderer(ctx, vox, frame, lv.settings(tile=tile, chunk=chunk, chunk_bwd=chunk_bwd))
     rgb, depth, alpha = r.new_outputs()
     P = frame.P
@@ -187,6 +187,83 @@ def test_aux_autograd_matches_direct_calls(ctx):
                np.concatenate([dd_ref.ravel(), dsh_ref.ravel()]))
     say(f"  autograd aux gradient rel-L2 {e:.2e}")
     assert e <= GRAD_TOL
+
+
+def _aux_grads(rng, P):
+    return (rng.normal(0, 1e-3, 3 * P), rng.normal(0, 1e-4, P), rng.normal(0, 1e-3, P),
+            rng.normal(0, 1e-2, P), rng.normal(0, 1e-3, 3 * P))
+
+
+def _aux_case(ctx, sc, cams, grads, ref_scene, tile, chunk, vox=None, bg=(0.0, 0.0, 0.0)):
+    """Forward channels and the full auxiliary gradient of one case, both
+    sides; returns the GPU gradients and the oracle's corner gradient."""
+    import torch
+    r, vox, frame, out = _render(ctx, sc, cams, tile, chunk, vox=vox, bg=bg)
+    ref = oracle.render_aux(ref_scene, cams, bg=bg)
+    got = {k: _np(v) for k, v in out.items()}
+    check_images(got, ref)
+    e_l = float(np.abs(got["dist"] - ref["dist"]).max())
+    e_n = float(np.abs(got["normal"] - ref["normal"]).max())
+    say(f"  dist {e_l:.2e} (max {ref['dist'].max():.3e})  normal {e_n:.2e}")
+    assert float(np.abs(got["wmax"] - ref["wmax"]).max()) <= WMAX_TOL
+    assert e_l <= IMG_TOL and e_n <= IMG_TOL
+    dev = ctx.device
+    dd, dsh = torch.empty_like(vox.density), torch.empty_like(vox.sh)
+    g = [to_dev(a, dev) for a in grads]
+    r.backward_aux(g[0], g[1], g[2], out["depth"], g[3], g[4], dd, dsh)
+    torch.cuda.synchronize()
+    dd_ref, dsh_ref = oracle.backward_aux(ref_scene, cams, *grads, bg=bg)
+    return _np(dd), _np(dsh), dd_ref, dsh_ref
+
+
+def test_aux_camera_inside_scene(ctx):
+    """The near plane cuts voxels around the camera; chords start at t = 0."""
+    sc = small_shell(5000, seed=85, deg=1, lmin=4, lmax=7, clutter=0.5)
+    cams = [look_at((0.05, 0.02, 0.79), 50, 40, target=(0.3, 0.1, -0.5)),
+            look_at((-0.1, 0.3, 0.2), 41, 37, target=(0.5, -0.6, 0.1))]
+    say("aux channels, camera inside the root cube")
+    grads = _aux_grads(np.random.default_rng(86), sum(c.npix for c in cams))
+    dd, dsh, dd_ref, dsh_ref = _aux_case(ctx, sc, cams, grads, sc, 8, 64)
+    e1, e2 = rel_l2(dd, dd_ref), rel_l2(dsh, dsh_ref)
+    say(f"  gradient rel-L2 density {e1:.2e} sh {e2:.2e}")
+    assert e1 <= GRAD_TOL and e2 <= GRAD_TOL
+
+
+def test_aux_with_background(ctx):
+    """The background enters the colour only: the normal channel carries no
+    background term and the distortion none either."""
+    sc, cams = _scene()
+    bg = (0.2, 0.5, 0.9)
+    say(f"aux channels, background {bg}")
+    grads = _aux_grads(np.random.default_rng(87), sum(c.npix for c in cams))
+    dd, dsh, dd_ref, dsh_ref = _aux_case(ctx, sc, cams, grads, sc, 16, 128, bg=bg)
+    e1, e2 = rel_l2(dd, dd_ref), rel_l2(dsh, dsh_ref)
+    say(f"  gradient rel-L2 density {e1:.2e} sh {e2:.2e}")
+    assert e1 <= GRAD_TOL and e2 <= GRAD_TOL
+
+
+def test_aux_grid_layout_softplus(ctx):
+    """Grid-point storage through softplus: the voxel normal and its
+    Jacobian act on the activated corner values, and the corner gradient is
+    scattered onto the stored grid values."""
+    import paper_2511_02510_amd as lv
+    import synth
+    from oracle import grid as ogrid
+    sc = small_shell(20000, seed=88, deg=1, lmin=5, lmax=9, clutter=0.1)
+    idx, ng = synth.grid_points(sc)
+    rng = np.random.default_rng(89)
+    raw = rng.normal(0.0, 1.0, ng).astype(np.float32)
+    cams = [look_at((2.0, 0.7, 1.2), 96, 72), look_at((-0.7, 1.2, -2.0), 80, 60)]
+    say(f"aux channels, grid layout through softplus: {sc.n} voxels on {ng} points")
+    vox = lv.Voxels.from_grid(sc, idx, raw, ctx.device, act=ogrid.ACT_SOFTPLUS)
+    dense = ogrid.with_corners(sc, ogrid.corner_values(raw, idx, ogrid.ACT_SOFTPLUS))
+    grads = _aux_grads(rng, sum(c.npix for c in cams))
+    dd, dsh, dc_ref, dsh_ref = _aux_case(ctx, sc, cams, grads, dense, 16, 64, vox=vox)
+    dd_ref = ogrid.grid_gradient(dc_ref, raw, idx, ogrid.ACT_SOFTPLUS)
+    assert dd.shape == (ng,)
+    e1, e2 = rel_l2(dd, dd_ref), rel_l2(dsh, dsh_ref)
+    say(f"  gradient rel-L2 grid values {e1:.2e} sh {e2:.2e}")
+    assert e1 <= GRAD_TOL and e2 <= GRAD_TOL
 
 
 def test_aux_argument_errors(ctx):
