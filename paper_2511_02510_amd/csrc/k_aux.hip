@@ -9,20 +9,22 @@
 // X_p = o + D_p d_p (d_p the pixel's unit ray), e_x = X(x+1,y) - X(x-1,y),
 // e_y = X(x,y+1) - X(x,y-1), m = (e_y x e_x) / |e_y x e_x| (0 if it vanishes),
 // which faces the camera for a visible surface.  Each term is multiplied by
-// its weight.  One thread per pixel; the depth gradient of a pixel gathers
-// the contributions of the (up to four) interior stencils that read it.
+// its weight.  The depth gradient of a pixel gathers the contributions of
+// the (up to four) interior stencils that read it.
 #include "lv_common.h"
 
 namespace lv {
 
 // unit world ray through the centre of pixel (x, y): R^T of the camera-space
-// direction, normalised
-__device__ __forceinline__ void aux_ray(const lv_camera& c, int x, int y, float d[3]) {
-  const float xc = ((float(x) + 0.5f) - c.cx) / c.fx;
-  const float yc = ((float(y) + 0.5f) - c.cy) / c.fy;
+// direction (with the reciprocal focal lengths ifx, ify), normalised with the
+// hardware reciprocal square root
+__device__ __forceinline__ void aux_ray(const lv_camera& c, float ifx, float ify, int x, int y,
+                                        float d[3]) {
+  const float xc = ((float(x) + 0.5f) - c.cx) * ifx;
+  const float yc = ((float(y) + 0.5f) - c.cy) * ify;
 #pragma unroll
   for (int a = 0; a < 3; ++a) d[a] = fmaf(c.R[a], xc, fmaf(c.R[3 + a], yc, c.R[6 + a]));
-  const float in = 1.0f / sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+  const float in = __builtin_amdgcn_rsqf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
   d[0] *= in; d[1] *= in; d[2] *= in;
 }
 
@@ -32,138 +34,221 @@ __device__ __forceinline__ void cross3(const float a[3], const float b[3], float
   c[2] = a[0] * b[1] - a[1] * b[0];
 }
 
-// The stencil of interior pixel (x, y): unit normal m and, for the weight
-// `scale` (= -lam_n / |I|) on N . m, the gradients gex, gey of the loss with
-// respect to the differences e_x, e_y.
-struct Stencil {
-  float m[3], gex[3], gey[3];
+// Tiles of TX x TY pixels, taken in turn by persistent blocks from one
+// index space over the tiles of every view.  A block stages, in LDS, the
+// camera-relative points D d of the tile grown by two pixels on each side,
+// then the stencil of every interior pixel of the tile grown by one (its
+// normal m and the gradients of the loss with respect to e_x and e_y), so
+// that each pixel's depth gradient gathers its four neighbours' stencils
+// from LDS: about 1.7 rays and 1.3 stencils per pixel instead of 21 and 5.
+// Every global value a tile reads is loaded at its start, in one round.
+constexpr int kTX = 32, kTY = 8;
+constexpr int kXW = kTX + 4, kXH = kTY + 4;   // points: tile +- 2
+constexpr int kSW = kTX + 2, kSH = kTY + 2;   // stencils: tile +- 1
+constexpr int kXN = kXW * kXH, kSN = kSW * kSH;
+static_assert(kTX * kTY == 256 && kXN <= 512 && kSN <= 512, "two slots per thread");
+
+struct AuxLds {
+  float X[3][kXN];
+  float m[3][kSN];
+  float gex[3][kSN];
+  float gey[3][kSN];
+  float part[3][4];
 };
 
-__device__ Stencil aux_stencil(const lv_camera& c, const float* D, const float* N, int W, int H,
-                               uint64_t npv, int x, int y, float scale) {
-  float dl[3], dr[3], du[3], dd[3];
-  aux_ray(c, x - 1, y, dl);
-  aux_ray(c, x + 1, y, dr);
-  aux_ray(c, x, y - 1, du);
-  aux_ray(c, x, y + 1, dd);
-  const float Dl = D[size_t(y) * W + x - 1], Dr = D[size_t(y) * W + x + 1];
-  const float Du = D[size_t(y - 1) * W + x], Dd = D[size_t(y + 1) * W + x];
-  float ex[3], ey[3], cr[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {   // the camera centre cancels in the differences
-    ex[a] = fmaf(Dr, dr[a], -Dl * dl[a]);
-    ey[a] = fmaf(Dd, dd[a], -Du * du[a]);
-  }
-  cross3(ey, ex, cr);
-  const float ln = sqrtf(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
-  Stencil s;
-  const size_t p = size_t(y) * W + x;
-  const float n[3] = {N[p], N[npv + p], N[2 * npv + p]};
-  if (!(ln > 0.0f)) {
-#pragma unroll
-    for (int a = 0; a < 3; ++a) s.m[a] = s.gex[a] = s.gey[a] = 0.0f;
-    return s;
-  }
-  const float il = 1.0f / ln;
-  float gm[3], gc[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    s.m[a] = cr[a] * il;
-    gm[a] = scale * n[a];
-  }
-  const float gmm = gm[0] * s.m[0] + gm[1] * s.m[1] + gm[2] * s.m[2];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) gc[a] = (gm[a] - gmm * s.m[a]) * il;
-  cross3(gc, ey, s.gex);   // d(e_y x e_x)/d e_x applied to gc
-  cross3(ex, gc, s.gey);   // d(e_y x e_x)/d e_y applied to gc
-  return s;
+// prefix of the tile counts over the views: view v owns tiles
+// [off[v], off[v + 1])
+struct AuxTiles {
+  uint32_t off[LV_MAX_VIEWS + 1];
+};
+
+struct AuxView {
+  lv_camera c;
+  int W, H, ntx;
+  size_t npv, pix;   // pixels of the view, offset of its first pixel
+  float inv_p, ni, wn, sc_n, ifx, ify;
+  bool has_int;
+};
+
+__device__ AuxView aux_view(const lv_camera* cams, int v, float lam_n) {
+  AuxView u;
+  u.c = cams[v];   // a private copy: the kernel's stores cannot alias it
+  u.W = u.c.width;
+  u.H = u.c.height;
+  u.ntx = (u.W + kTX - 1) / kTX;
+  u.npv = size_t(u.W) * size_t(u.H);
+  u.pix = 0;
+  for (int k = 0; k < v; ++k) u.pix += size_t(cams[k].width) * size_t(cams[k].height);
+  u.has_int = u.W >= 3 && u.H >= 3;
+  u.ni = u.has_int ? float(u.W - 2) * float(u.H - 2) : 1.0f;
+  u.inv_p = float(1.0 / double(u.npv));
+  u.wn = u.has_int ? lam_n / u.ni : 0.0f;   // weight of each interior pixel's term
+  u.sc_n = -u.wn;                           // weight of N . m in the loss
+  u.ifx = 1.0f / u.c.fx;
+  u.ify = 1.0f / u.c.fy;
+  return u;
 }
 
-__global__ __launch_bounds__(256) void k_aux_loss(const lv_camera* cams, const float* depth,
-                                                  const float* alpha, const float* normal,
-                                                  const float* dist, float lam_tc, float lam_n,
-                                                  float lam_d, float* loss, float* g_alpha,
-                                                  float* g_depth, float* g_normal, float* g_dist) {
-  __shared__ float s_part[3][4];
-  const int v = blockIdx.y;
-  const lv_camera& c = cams[v];
-  const int W = c.width, H = c.height;
-  const uint64_t npv = uint64_t(W) * uint64_t(H);
-  uint64_t off = 0;
-  for (int u = 0; u < v; ++u) off += uint64_t(cams[u].width) * uint64_t(cams[u].height);
-  const float* D = depth + off;
-  const float* A = alpha + off;
-  const float* N = normal + 3 * off;
-  const float* L = dist + off;
-  const bool has_int = W >= 3 && H >= 3;
-  const float ni = has_int ? float(W - 2) * float(H - 2) : 1.0f;
-  const float inv_p = float(1.0 / double(npv));
-  const float sc_n = -lam_n / ni;   // weight of N . m in the loss
-  float p_tc = 0.0f, p_n = 0.0f, p_d = 0.0f;
-  for (uint64_t p = uint64_t(blockIdx.x) * 256u + threadIdx.x; p < npv;
-       p += uint64_t(gridDim.x) * 256u) {
-    const int x = int(p % uint64_t(W)), y = int(p / uint64_t(W));
-    const float a = A[p];
-    p_tc = fmaf(a, 1.0f - a, p_tc);
-    p_d += L[p];
-    float ga = lam_tc * (1.0f - 2.0f * a) * inv_p;
-    float gn[3] = {0.0f, 0.0f, 0.0f};
-    const bool in = has_int && x >= 1 && x <= W - 2 && y >= 1 && y <= H - 2;
-    if (in) {
-      const Stencil s = aux_stencil(c, D, N, W, H, npv, x, y, sc_n);
-      p_n += a - (N[p] * s.m[0] + N[npv + p] * s.m[1] + N[2 * npv + p] * s.m[2]);
-      ga += lam_n / ni;
-#pragma unroll
-      for (int k = 0; k < 3; ++k) gn[k] = sc_n * s.m[k];
-    }
-    // this pixel's depth enters the stencils of its four neighbours
-    float gX[3] = {0.0f, 0.0f, 0.0f};
-    if (has_int) {
-      if (x - 1 >= 1 && x - 1 <= W - 2 && y >= 1 && y <= H - 2) {   // it is X(x+1) of (x-1, y)
-        const Stencil s = aux_stencil(c, D, N, W, H, npv, x - 1, y, sc_n);
-        for (int k = 0; k < 3; ++k) gX[k] += s.gex[k];
-      }
-      if (x + 1 >= 1 && x + 1 <= W - 2 && y >= 1 && y <= H - 2) {   // X(x-1) of (x+1, y)
-        const Stencil s = aux_stencil(c, D, N, W, H, npv, x + 1, y, sc_n);
-        for (int k = 0; k < 3; ++k) gX[k] -= s.gex[k];
-      }
-      if (y - 1 >= 1 && y - 1 <= H - 2 && x >= 1 && x <= W - 2) {   // X(y+1) of (x, y-1)
-        const Stencil s = aux_stencil(c, D, N, W, H, npv, x, y - 1, sc_n);
-        for (int k = 0; k < 3; ++k) gX[k] += s.gey[k];
-      }
-      if (y + 1 >= 1 && y + 1 <= H - 2 && x >= 1 && x <= W - 2) {   // X(y-1) of (x, y+1)
-        const Stencil s = aux_stencil(c, D, N, W, H, npv, x, y + 1, sc_n);
-        for (int k = 0; k < 3; ++k) gX[k] -= s.gey[k];
-      }
-    }
-    float dp[3];
-    aux_ray(c, x, y, dp);
-    g_alpha[off + p] = ga;
-    g_depth[off + p] = gX[0] * dp[0] + gX[1] * dp[1] + gX[2] * dp[2];
-    g_normal[3 * off + p] = gn[0];
-    g_normal[3 * off + npv + p] = gn[1];
-    g_normal[3 * off + 2 * npv + p] = gn[2];
-    g_dist[off + p] = lam_d * inv_p;
-  }
+// block sum of the three partial terms of view v, weighted, into loss[3 v ..]
+__device__ void aux_flush(AuxLds& L, float p[3], const AuxView& u, int v, float lam_tc,
+                          float lam_d, float* loss) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    p_tc += __shfl_xor(p_tc, o, 64);
-    p_n += __shfl_xor(p_n, o, 64);
-    p_d += __shfl_xor(p_d, o, 64);
-  }
-  if (lane == 0) {
-    s_part[0][wv] = p_tc;
-    s_part[1][wv] = p_n;
-    s_part[2][wv] = p_d;
+  for (int k = 0; k < 3; ++k) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) p[k] += __shfl_xor(p[k], o, 64);
+    if (lane == 0) L.part[k][wv] = p[k];
+    p[k] = 0.0f;
   }
   __syncthreads();
   if (threadIdx.x < 3) {
     const int k = threadIdx.x;
-    const float t = (s_part[k][0] + s_part[k][1]) + (s_part[k][2] + s_part[k][3]);
-    const float f = k == 0 ? lam_tc * inv_p : (k == 1 ? (has_int ? lam_n / ni : 0.0f) : lam_d * inv_p);
+    const float t = (L.part[k][0] + L.part[k][1]) + (L.part[k][2] + L.part[k][3]);
+    const float f = k == 0 ? lam_tc * u.inv_p : (k == 1 ? u.wn : lam_d * u.inv_p);
     unsafeAtomicAdd(&loss[3 * v + k], t * f);
   }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_aux_loss(const lv_camera* cams, AuxTiles tl, int V,
+                                                  const float* depth, const float* alpha,
+                                                  const float* normal, const float* dist,
+                                                  float lam_tc, float lam_n, float lam_d,
+                                                  float* loss, float* g_alpha, float* g_depth,
+                                                  float* g_normal, float* g_dist) {
+  __shared__ AuxLds L;
+  const uint32_t total = tl.off[V];
+  int v = -1;
+  AuxView u;
+  float part[3] = {0.0f, 0.0f, 0.0f};
+  const int lx = threadIdx.x % kTX, ly = threadIdx.x / kTX;
+  for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
+    int nv = v < 0 ? 0 : v;   // the views are visited in increasing order
+    while (tl.off[nv + 1] <= t) ++nv;
+    if (nv != v) {
+      if (v >= 0) aux_flush(L, part, u, v, lam_tc, lam_d, loss);
+      v = nv;
+      u = aux_view(cams, v, lam_n);
+    }
+    const uint32_t tt = t - tl.off[v];
+    const int x0 = int(tt % uint32_t(u.ntx)) * kTX, y0 = int(tt / uint32_t(u.ntx)) * kTY;
+    const int W = u.W, H = u.H;
+    const size_t npv = u.npv;
+    const float* D = depth + u.pix;
+    const float* N = normal + 3 * u.pix;
+    // ---- every load of the tile: depth at two point slots, the rendered
+    // normal at two stencil slots and at this thread's pixel, alpha, dist
+    float dep[2], ns[2][3];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int i = threadIdx.x + 256 * j;
+      const int gx = x0 - 2 + i % kXW, gy = y0 - 2 + i / kXW;
+      dep[j] = (i < kXN && gx >= 0 && gx < W && gy >= 0 && gy < H) ? D[size_t(gy) * W + gx] : 0.0f;
+      const int sx = x0 - 1 + i % kSW, sy = y0 - 1 + i / kSW;
+      const bool in = i < kSN && sx >= 1 && sx <= W - 2 && sy >= 1 && sy <= H - 2;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) ns[j][a] = in ? N[a * npv + size_t(sy) * W + sx] : 0.0f;
+    }
+    const int x = x0 + lx, y = y0 + ly;
+    const bool mine = x < W && y < H;
+    const size_t p = size_t(y) * W + x;
+    float a = 0.0f, ld = 0.0f, n0 = 0.0f, n1 = 0.0f, n2 = 0.0f;
+    if (mine) {
+      a = alpha[u.pix + p];
+      ld = dist[u.pix + p];
+      n0 = N[p];
+      n1 = N[npv + p];
+      n2 = N[2 * npv + p];
+    }
+    // ---- points X = D d (the camera centre cancels in every difference)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int i = threadIdx.x + 256 * j;
+      if (i < kXN) {
+        const int gx = x0 - 2 + i % kXW, gy = y0 - 2 + i / kXW;
+        float d[3] = {0.0f, 0.0f, 0.0f};
+        if (gx >= 0 && gx < W && gy >= 0 && gy < H) aux_ray(u.c, u.ifx, u.ify, gx, gy, d);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) L.X[k][i] = dep[j] * d[k];
+      }
+    }
+    __syncthreads();
+    // ---- stencils of the interior pixels among tile +- 1 (zero elsewhere)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int i = threadIdx.x + 256 * j;
+      if (i < kSN) {
+        const int sx = i % kSW, sy = i / kSW;
+        const int gx = x0 - 1 + sx, gy = y0 - 1 + sy;
+        float m[3] = {0.0f, 0.0f, 0.0f}, gex[3] = {0.0f, 0.0f, 0.0f}, gey[3] = {0.0f, 0.0f, 0.0f};
+        if (gx >= 1 && gx <= W - 2 && gy >= 1 && gy <= H - 2) {
+          const int xc = (sy + 1) * kXW + sx + 1;   // this pixel in the point block
+          float ex[3], ey[3], cr[3];
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            ex[k] = L.X[k][xc + 1] - L.X[k][xc - 1];
+            ey[k] = L.X[k][xc + kXW] - L.X[k][xc - kXW];
+          }
+          cross3(ey, ex, cr);
+          const float l2 = cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2];
+          // below the smallest normal float the stencil counts as degenerate
+          // (m = 0), which keeps the reciprocal square root finite
+          if (l2 >= 1.17549435e-38f) {
+            const float il = __builtin_amdgcn_rsqf(l2);
+            float gm[3], gc[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+              m[k] = cr[k] * il;
+              gm[k] = u.sc_n * ns[j][k];
+            }
+            const float gmm = gm[0] * m[0] + gm[1] * m[1] + gm[2] * m[2];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) gc[k] = (gm[k] - gmm * m[k]) * il;
+            cross3(gc, ey, gex);   // d(e_y x e_x)/d e_x applied to gc
+            cross3(ex, gc, gey);   // d(e_y x e_x)/d e_y applied to gc
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          L.m[k][i] = m[k];
+          L.gex[k][i] = gex[k];
+          L.gey[k][i] = gey[k];
+        }
+      }
+    }
+    __syncthreads();
+    // ---- this thread's pixel
+    if (mine) {
+      part[0] = fmaf(a, 1.0f - a, part[0]);
+      part[2] += ld;
+      float ga = lam_tc * (1.0f - 2.0f * a) * u.inv_p;
+      const int sc = (ly + 1) * kSW + lx + 1;   // this pixel in the stencil block
+      float gn[3] = {0.0f, 0.0f, 0.0f};
+      if (x >= 1 && x <= W - 2 && y >= 1 && y <= H - 2) {
+        part[1] += a - (n0 * L.m[0][sc] + n1 * L.m[1][sc] + n2 * L.m[2][sc]);
+        ga += u.wn;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) gn[k] = u.sc_n * L.m[k][sc];
+      }
+      // this pixel is X(x+1) of (x-1, y), X(x-1) of (x+1, y), X(y+1) of
+      // (x, y-1) and X(y-1) of (x, y+1); stencils outside the interior are 0
+      float gX[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        gX[k] = (L.gex[k][sc - 1] - L.gex[k][sc + 1]) + (L.gey[k][sc - kSW] - L.gey[k][sc + kSW]);
+      float dp[3];
+      aux_ray(u.c, u.ifx, u.ify, x, y, dp);
+      g_alpha[u.pix + p] = ga;
+      g_depth[u.pix + p] = gX[0] * dp[0] + gX[1] * dp[1] + gX[2] * dp[2];
+      float* gnv = g_normal + 3 * u.pix + p;
+      gnv[0] = gn[0];
+      gnv[npv] = gn[1];
+      gnv[2 * npv] = gn[2];
+      g_dist[u.pix + p] = lam_d * u.inv_p;
+    }
+    __syncthreads();   // the next tile overwrites the blocks
+  }
+  if (v >= 0) aux_flush(L, part, u, v, lam_tc, lam_d, loss);
 }
 
 __global__ void k_aux_zero(float* loss, int n) {
@@ -171,15 +256,34 @@ __global__ void k_aux_zero(float* loss, int n) {
   if (i < n) loss[i] = 0.0f;
 }
 
-hipError_t run_aux_loss(const lv_camera* cams_dev, int V, uint64_t max_pix, const float* depth,
-                        const float* alpha, const float* normal, const float* dist, float lam_tc,
-                        float lam_n, float lam_d, float* loss, float* g_alpha, float* g_depth,
-                        float* g_normal, float* g_dist, hipStream_t s) {
+hipError_t run_aux_loss(const lv_camera* cams_host, const lv_camera* cams_dev, int V,
+                        const float* depth, const float* alpha, const float* normal,
+                        const float* dist, float lam_tc, float lam_n, float lam_d, float* loss,
+                        float* g_alpha, float* g_depth, float* g_normal, float* g_dist,
+                        hipStream_t s) {
+  if (V < 1 || V > LV_MAX_VIEWS) return hipErrorInvalidValue;
+  AuxTiles tl;
+  tl.off[0] = 0;
+  uint64_t total = 0;
+  for (int v = 0; v < V; ++v) {
+    total += ((uint64_t(cams_host[v].width) + kTX - 1) / kTX) *
+             ((uint64_t(cams_host[v].height) + kTY - 1) / kTY);
+    if (total > 0xffffffffull) return hipErrorInvalidValue;
+    tl.off[v + 1] = uint32_t(total);
+  }
   hipLaunchKernelGGL(k_aux_zero, dim3((3 * V + 255) / 256), dim3(256), 0, s, loss, 3 * V);
-  uint64_t b = (max_pix + 255) / 256;
-  if (b > 256) b = 256;   // each block ends with one atomic per term
+  // persistent: as many blocks as fit on the device at once
+  int dev = 0, cus = 256, per = 1;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    cus = 256;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_aux_loss, 256, 0) != hipSuccess ||
+      per < 1)
+    per = 1;
+  uint64_t b = uint64_t(cus) * uint64_t(per);
+  if (b > total) b = total;
   if (b < 1) b = 1;
-  hipLaunchKernelGGL(k_aux_loss, dim3(uint32_t(b), V), dim3(256), 0, s, cams_dev, depth, alpha,
+  hipLaunchKernelGGL(k_aux_loss, dim3(uint32_t(b)), dim3(256), 0, s, cams_dev, tl, V, depth, alpha,
                      normal, dist, lam_tc, lam_n, lam_d, loss, g_alpha, g_depth, g_normal, g_dist);
   return hipGetLastError();
 }

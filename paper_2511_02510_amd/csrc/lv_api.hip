@@ -613,7 +613,7 @@ lv_status lv_aux_loss(lv_context* ctx, const lv_frame* frame, const float* depth
   if (!depth || !alpha || !normal || !dist || !loss || !d_alpha || !d_depth || !d_normal ||
       !d_dist)
     return fail(ctx, LV_ERR_ARG, "lv_aux_loss: every pointer must be non-NULL");
-  LV_TRY(lv::run_aux_loss(frame->cams_dev, frame->n_views, max_view_pixels(frame), depth, alpha,
+  LV_TRY(lv::run_aux_loss(frame->cams_host, frame->cams_dev, frame->n_views, depth, alpha,
                           normal, dist, lam_tc, lam_n, lam_d, loss, d_alpha, d_depth, d_normal,
                           d_dist, stream), "aux_loss");
   return LV_OK;

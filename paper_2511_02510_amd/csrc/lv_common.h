@@ -366,10 +366,11 @@ struct FillSet {   // word ranges filled by one launch
 };
 hipError_t launch_fill_set(const FillSet& f, hipStream_t s);
 hipError_t launch_preprocess(const RasterArgs& a, hipStream_t s);
-hipError_t run_aux_loss(const lv_camera* cams_dev, int V, uint64_t max_pix, const float* depth,
-                        const float* alpha, const float* normal, const float* dist, float lam_tc,
-                        float lam_n, float lam_d, float* loss, float* g_alpha, float* g_depth,
-                        float* g_normal, float* g_dist, hipStream_t s);
+hipError_t run_aux_loss(const lv_camera* cams_host, const lv_camera* cams_dev, int V,
+                        const float* depth, const float* alpha, const float* normal,
+                        const float* dist, float lam_tc, float lam_n, float lam_d, float* loss,
+                        float* g_alpha, float* g_depth, float* g_normal, float* g_dist,
+                        hipStream_t s);
 hipError_t launch_count_records(const Rec* rec, uint64_t nrec, unsigned long long* out,
                                 hipStream_t s);
 hipError_t launch_scan_tiles(const RasterArgs& a, uint32_t nblk, hipStream_t s);

@@ -104,8 +104,10 @@ def test_aux_backward_matches_oracle(ctx, which):
 def test_aux_loss_kernel_matches_oracle(ctx):
     import torch
     import paper_2511_02510_amd as lv
+    # ragged tiles, a view without interior pixels, and a view of more tiles
+    # (11 x 33) than the kernel launches blocks per view
     cams = [look_at((0.3, 0.4, -2.5), 64, 48), look_at((2.0, 0.1, 0.5), 37, 29),
-            look_at((1.0, 1.0, 1.0), 2, 9)]
+            look_at((1.0, 1.0, 1.0), 2, 9), look_at((-1.5, 0.7, 2.0), 331, 259)]
     frame = lv.Frame(cams, ctx.device)
     P = frame.P
     rng = np.random.default_rng(83)
