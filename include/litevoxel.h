@@ -227,10 +227,12 @@ lv_status lv_backward_aux(lv_context* ctx, const lv_voxels* vox, const lv_frame*
  * with I_v the interior pixels (1 <= x <= W-2, 1 <= y <= H-2; none when W or
  * H < 3) and m the unit normal of the surface of the depth channel: X = o +
  * D d (d the pixel's unit ray), m = normalise((X(x,y+1) - X(x,y-1)) x
- * (X(x+1,y) - X(x-1,y))) (0 if that vanishes), facing the camera.  Writes
- * (overwrites) loss [3 n_views] (device) and the gradients of the summed
- * losses: d_alpha, d_depth, d_dist [P] and d_normal (rgb layout).  All
- * pointers non-NULL. */
+ * (X(x+1,y) - X(x-1,y))) (0 when the cross product's squared length is below
+ * the smallest normal float), facing the camera.  Writes (overwrites) loss
+ * [3 n_views] (device; each term summed with float atomics in no fixed order,
+ * so the last bits may vary between calls) and the gradients of the summed
+ * losses: d_alpha, d_depth, d_dist [P] and d_normal (rgb layout), which are
+ * deterministic.  All pointers non-NULL. */
 lv_status lv_aux_loss(lv_context* ctx, const lv_frame* frame, const float* depth,
                       const float* alpha, const float* normal, const float* dist, float lam_tc,
                       float lam_n, float lam_d, float* loss, float* d_alpha, float* d_depth,

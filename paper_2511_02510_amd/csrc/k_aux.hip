@@ -7,8 +7,9 @@
 // with I the interior pixels (1 <= x <= W-2, 1 <= y <= H-2), N the rendered
 // normal and m the unit normal of the surface the depth channel describes:
 // X_p = o + D_p d_p (d_p the pixel's unit ray), e_x = X(x+1,y) - X(x-1,y),
-// e_y = X(x,y+1) - X(x,y-1), m = (e_y x e_x) / |e_y x e_x| (0 if it vanishes),
-// which faces the camera for a visible surface.  Each term is multiplied by
+// e_y = X(x,y+1) - X(x,y-1), m = (e_y x e_x) / |e_y x e_x| (0 when the
+// cross product vanishes; here, when its squared length is below the smallest
+// normal float), which faces the camera for a visible surface.  Each term is multiplied by
 // its weight.  The depth gradient of a pixel gathers the contributions of
 // the (up to four) interior stencils that read it.
 #include "lv_common.h"
