@@ -42,7 +42,10 @@ __device__ __forceinline__ void cross3(const float a[3], const float b[3], float
 // normal m and the gradients of the loss with respect to e_x and e_y), so
 // that each pixel's depth gradient gathers its four neighbours' stencils
 // from LDS: about 1.7 rays and 1.3 stencils per pixel instead of 21 and 5.
-// Every global value a tile reads is loaded at its start, in one round.
+// Every global value a tile reads is loaded at its start, in one round.  The
+// kernel is bound by memory latency, not arithmetic: keeping each XCD on one
+// contiguous run of tiles (halo rows stay in its L2) and loading the view
+// sizes in parallel are what shortened it.
 constexpr int kTX = 32, kTY = 8;
 constexpr int kXW = kTX + 4, kXH = kTY + 4;   // points: tile +- 2
 constexpr int kSW = kTX + 2, kSH = kTY + 2;   // stencils: tile +- 1
@@ -78,8 +81,14 @@ __device__ AuxView aux_view(const lv_camera* cams, int v, float lam_n) {
   u.H = u.c.height;
   u.ntx = (u.W + kTX - 1) / kTX;
   u.npv = size_t(u.W) * size_t(u.H);
-  u.pix = 0;
-  for (int k = 0; k < v; ++k) u.pix += size_t(cams[k].width) * size_t(cams[k].height);
+  // pixels of the views before v: the lanes load the view sizes in parallel
+  // (a loop over the views would wait for one load after another)
+  unsigned long long pix = 0;
+  for (int k = threadIdx.x & 63; k < v; k += 64)
+    pix += (unsigned long long)(cams[k].width) * (unsigned long long)(cams[k].height);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) pix += __shfl_xor(pix, o, 64);
+  u.pix = size_t(pix);
   u.has_int = u.W >= 3 && u.H >= 3;
   u.ni = u.has_int ? float(u.W - 2) * float(u.H - 2) : 1.0f;
   u.inv_p = float(1.0 / double(u.npv));
@@ -123,7 +132,15 @@ __global__ __launch_bounds__(256) void k_aux_loss(const lv_camera* cams, AuxTile
   AuxView u;
   float part[3] = {0.0f, 0.0f, 0.0f};
   const int lx = threadIdx.x % kTX, ly = threadIdx.x / kTX;
-  for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
+  // XCD-aware: blocks are dealt to the 8 XCDs round-robin; the blocks of one
+  // XCD sweep one contiguous eighth of the tiles, so the halo rows a tile
+  // shares with its neighbours stay in that XCD's L2
+  const uint32_t nseg = gridDim.x < 8u ? gridDim.x : 8u;
+  const uint32_t seg = blockIdx.x % nseg, kb = blockIdx.x / nseg;
+  const uint32_t gseg = (gridDim.x - seg + nseg - 1) / nseg;   // blocks of this segment
+  const uint32_t t0 = uint32_t((uint64_t(total) * seg) / nseg);
+  const uint32_t t1 = uint32_t((uint64_t(total) * (seg + 1)) / nseg);
+  for (uint32_t t = t0 + kb; t < t1; t += gseg) {
     int nv = v < 0 ? 0 : v;   // the views are visited in increasing order
     while (tl.off[nv + 1] <= t) ++nv;
     if (nv != v) {
