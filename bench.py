@@ -234,6 +234,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-views", type=int, default=8,
                     help="views of the workload the oracle baseline renders (8 = the whole step)")
+    ap.add_argument("--profile-aux-steps", type=int, default=0,
+                    help="run this many steps with the auxiliary channels and terms on one "
+                         "stream and exit (for kernel traces)")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="if > 0: only run this many eager steps (for rocprofv3) and exit")
     ap.add_argument("--other-workloads", default="grid4k,shell200k,shell200k_train,hemi4m",
@@ -317,6 +320,31 @@ def main():
     fits, Q = lv.check_overflow(ctx, vox, frame, r.st, r.saved, stream=stream)
     assert fits
     log(f"[bench] pairs Q={Q} capacity={r.st.pair_capacity}")
+
+    # buffers of the step with the auxiliary channels and terms: forward with
+    # the distortion and normal channels, loss weight, L1, the three
+    # auxiliary terms, one backward taking every channel's gradient
+    dist_c, normal_c = torch.empty(P, device=dev), torch.empty(3 * P, device=dev)
+    aloss = torch.empty(3 * len(cams), device=dev)
+    ga_c, gd_c, gl_c = (torch.empty(P, device=dev) for _ in range(3))
+    gn_c = torch.empty(3 * P, device=dev)
+
+    def aux_step(verify=False):
+        lv.lf_weight(ctx, frame, target, gamma, 0, 1e-3, weight, lw_ws, stream=stream)
+        r.forward(rgb, depth, alpha, wmax, stream=stream, verify=verify, dist=dist_c,
+                  normal=normal_c)
+        lv.l1_grad(ctx, frame, rgb, target, weight, loss, d_rgb, stream=stream)
+        lv.aux_loss(ctx, frame, depth, alpha, normal_c, dist_c, 0.01, 0.05, 1.0, aloss, ga_c,
+                    gd_c, gn_c, gl_c, stream=stream)
+        r.backward_aux(d_rgb, gd_c, ga_c, depth, gl_c, gn_c, d_density, d_sh, stream=stream)
+
+    if args.profile_aux_steps > 0:
+        aux_step(verify=True)
+        for _ in range(args.profile_aux_steps):
+            aux_step()
+        torch.cuda.synchronize()
+        log("[bench] auxiliary profile steps done")
+        return
 
     if args.profile_steps > 0:
         for _ in range(args.profile_steps):
@@ -485,20 +513,6 @@ def main():
     # ---- the auxiliary channels and terms on this workload: forward with the
     # distortion and normal channels, loss weight, L1, the three auxiliary
     # terms, one backward taking every channel's gradient
-    dist_c, normal_c = torch.empty(P, device=dev), torch.empty(3 * P, device=dev)
-    aloss = torch.empty(3 * len(cams), device=dev)
-    ga_c, gd_c, gl_c = (torch.empty(P, device=dev) for _ in range(3))
-    gn_c = torch.empty(3 * P, device=dev)
-
-    def aux_step(verify=False):
-        lv.lf_weight(ctx, frame, target, gamma, 0, 1e-3, weight, lw_ws, stream=stream)
-        r.forward(rgb, depth, alpha, wmax, stream=stream, verify=verify, dist=dist_c,
-                  normal=normal_c)
-        lv.l1_grad(ctx, frame, rgb, target, weight, loss, d_rgb, stream=stream)
-        lv.aux_loss(ctx, frame, depth, alpha, normal_c, dist_c, 0.01, 0.05, 1.0, aloss, ga_c,
-                    gd_c, gn_c, gl_c, stream=stream)
-        r.backward_aux(d_rgb, gd_c, ga_c, depth, gl_c, gn_c, d_density, d_sh, stream=stream)
-
     aux_step(verify=True)
     torch.cuda.synchronize()
     lv.set_timing(ctx, True)
@@ -508,9 +522,12 @@ def main():
     aph = lv.read_timings(ctx)
     lv.set_timing(ctx, False)
     aphases = {k: (ms / max(c, 1)) for k, (ms, c) in aph.items()}
-    t_aux_loss = gpu_ms(lambda: lv.aux_loss(ctx, frame, depth, alpha, normal_c, dist_c, 0.01, 0.05,
-                                            1.0, aloss, ga_c, gd_c, gn_c, gl_c, stream=stream),
-                        max(5, args.steps // 2))
+    # ten calls back to back per timed interval, so host-side gaps between
+    # the event and the launch do not count
+    t_aux_loss = gpu_ms(lambda: [lv.aux_loss(ctx, frame, depth, alpha, normal_c, dist_c, 0.01,
+                                             0.05, 1.0, aloss, ga_c, gd_c, gn_c, gl_c,
+                                             stream=stream) for _ in range(10)],
+                        max(5, args.steps // 2)) / 10
     lv.graph_begin(ctx, stream)
     aux_step()
     lv.graph_end(ctx, stream)
