@@ -191,3 +191,15 @@ def test_autotune_cache_key_and_hit_without_device(tmp_path):
     best, table = lv.autotune(None, vox, frame, cache=str(path))
     assert (best.tile, best.chunk, best.chunk_bwd, best.pair_capacity) == (8, 128, 64, 0)
     assert table.shape == (2, 3, 3) and table[0, 2, 2] == 8 and table[1, 0, 0] == 9
+
+
+def test_aux_entry_points_reject_a_null_context():
+    lib = _abi.lib()
+    vox, fr, st = _vox_frame()
+    p = ctypes.c_void_p(0x3000)
+    assert lib.lv_forward_aux(None, ctypes.byref(vox), ctypes.byref(fr), ctypes.byref(st), p, p, p,
+                              p, p, p, p, p, None) == _abi.LV_ERR_ARG
+    assert lib.lv_backward_aux(None, ctypes.byref(vox), ctypes.byref(fr), ctypes.byref(st), p, p,
+                               p, p, p, p, p, p, p, p, None) == _abi.LV_ERR_ARG
+    assert lib.lv_aux_loss(None, ctypes.byref(fr), p, p, p, p, 1.0, 1.0, 1.0, p, p, p, p, p,
+                           None) == _abi.LV_ERR_ARG

@@ -278,3 +278,9 @@ def test_aux_argument_errors(ctx):
     g = torch.zeros(P, device=ctx.device)
     with pytest.raises(lv.LiteVoxelError):   # d_dist without the forward's depth
         r.backward_aux(torch.zeros(3 * P, device=ctx.device), None, None, None, g, None, dd, dsh)
+    loss = torch.empty(3 * frame.n_views, device=ctx.device)
+    bufs = [torch.empty(P, device=ctx.device), torch.empty(P, device=ctx.device),
+            torch.empty(3 * P, device=ctx.device), torch.empty(P, device=ctx.device)]
+    with pytest.raises(lv.LiteVoxelError):   # every pointer of lv_aux_loss is required
+        lv.aux_loss(ctx, frame, out["depth"], out["alpha"], out["normal"], out["dist"], 1.0, 1.0,
+                    1.0, loss, bufs[0], None, bufs[2], bufs[3])
