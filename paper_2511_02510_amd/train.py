@@ -251,13 +251,119 @@ def training_problem(ctx: lv.Context, n_gt: int = 60000, views: int = 6, res=(19
     return lv.Voxels.from_scene(init, dev), frame, target, gt, cams
 
 
+def layered_scene(seed: int = 11):
+    """An opaque inner shell (radius 0.25-0.35, 20k leaves, densities x20)
+    inside a semi-transparent outer shell (radius 0.8-0.95, 30k leaves):
+    the outer shell's voxels sit in their own depth ranges (its near and far
+    sides) with low blending weights.  Returns (scene, is_outer [N] bool)."""
+    import synth
+    from synth.scenes import Scene, octree_order
+    rng = np.random.default_rng(seed)
+    inner = synth.make_scene_shell(rng, 20000, 6, 9, sh_degree=1, clutter_frac=0.0, r_lo=0.25,
+                                   r_hi=0.35)
+    outer = synth.make_scene_shell(rng, 30000, 5, 9, sh_degree=1, clutter_frac=0.0, r_lo=0.8,
+                                   r_hi=0.95)
+    inner.density = (inner.density * 20.0).astype(np.float32)
+    ijk = np.concatenate([inner.ijk, outer.ijk], 1)
+    level = np.concatenate([inner.level, outer.level])
+    p = octree_order(ijk, level)
+    tag = np.concatenate([np.zeros(inner.n, bool), np.ones(outer.n, bool)])[p]
+    sc = Scene(root_min=inner.root_min.copy(), root_size=inner.root_size,
+               ijk=np.ascontiguousarray(ijk[:, p]), level=np.ascontiguousarray(level[p]),
+               density=np.ascontiguousarray(np.concatenate([inner.density, outer.density], 1)[:, p]),
+               sh=np.ascontiguousarray(np.concatenate([inner.sh, outer.sh], 1)[:, p]),
+               sh_degree=1)
+    return sc, tag, inner, outer
+
+
+def pruning_study(ctx: lv.Context, q: float = 0.2, rounds: int = 3, n_bins: int = 16) -> dict:
+    """Pruning alone, on the ground truth of the layered scene: `rounds`
+    times, render w_max and remove the voxels a rule marks, with the global
+    nearest-rank q-quantile of w_max and with the per-bin depth quantile of
+    eq. 11-12 (no guards); then compare the remaining voxels (inner / outer
+    shell) and the PSNR of the pruned model against the unpruned images, on
+    all pixels, on the pixels the inner shell covers and on those only the
+    outer shell covers."""
+    from synth.scenes import look_at
+    sc, tag, inner, outer = layered_scene()
+    dev = ctx.device
+    cams = []
+    for i in range(6):
+        az = 2 * math.pi * i / 6 + 0.31
+        el = 0.35 + 0.25 * math.sin(1.3 * i)
+        o = (2.6 * math.cos(el) * math.cos(az), 2.6 * math.sin(el), 2.6 * math.cos(el) * math.sin(az))
+        cams.append(look_at(o, 192, 144))
+    frame = lv.Frame(cams, dev)
+
+    def render(vox):
+        r = lv.Renderer(ctx, vox, frame)
+        rgb, depth, alpha = r.new_outputs()
+        w = torch.zeros(vox.n, device=dev)
+        r.forward(rgb, depth, alpha, w)
+        return rgb, alpha, w
+
+    target, _, _ = render(lv.Voxels.from_scene(sc, dev))
+    _, a_in, _ = render(lv.Voxels.from_scene(inner, dev))
+    _, a_out, _ = render(lv.Voxels.from_scene(outer, dev))
+    regions = {"inner_px": a_in > 0.5, "outer_only_px": (a_in < 0.01) & (a_out > 0.02)}
+
+    def rgb_mask(mask):   # pixel mask -> rgb layout ([3][H][W] per view)
+        parts, off = [], 0
+        for c in cams:
+            m = mask[off:off + c.npix]
+            parts += [m, m, m]
+            off += c.npix
+        return torch.cat(parts)
+
+    def psnr_of(rgb, mask=None):
+        d = rgb - target if mask is None else (rgb - target)[rgb_mask(mask)]
+        return -10.0 * math.log10(max(float(torch.mean(d * d)), 1e-12))
+
+    out = {"scene": "opaque inner shell (20k leaves) in a semi-transparent outer shell (30k)",
+           "q": q, "rounds": rounds,
+           "pixels": {k: int(v.sum()) for k, v in regions.items()}}
+    for mode in ("global", "depth_quantile"):
+        vox = lv.Voxels.from_scene(sc, dev)
+        t = torch.from_numpy(tag).to(dev)
+        for _ in range(rounds):
+            _, _, w = render(vox)
+            n = vox.n
+            if mode == "global":
+                k = min(max(int(math.ceil(q * n)), 1), n)
+                prune = w <= torch.kthvalue(w, k).values
+            else:
+                qws = torch.empty(lv.quantile_workspace_size(n, n_bins), dtype=torch.uint8,
+                                  device=dev)
+                tau = torch.empty(n_bins, device=dev)
+                pm = torch.empty(n, dtype=torch.uint8, device=dev)
+                lv.depth_quantile(ctx, vox, frame, w, n_bins, q, qws, tau, pm)
+                prune = pm != 0
+            keep = ~prune
+            vox = lv.Voxels(vox.ijk[:, keep].contiguous(), vox.level[keep].contiguous(),
+                            vox.density[:, keep].contiguous(), vox.sh[:, keep].contiguous(),
+                            vox.root_min, vox.root_size, vox.sh_degree)
+            t = t[keep]
+        rgb, _, _ = render(vox)
+        out[mode] = {"voxels": vox.n, "inner": int((~t).sum()), "outer": int(t.sum()),
+                     "psnr": round(psnr_of(rgb), 2),
+                     "psnr_inner_px": round(psnr_of(rgb, regions["inner_px"]), 2),
+                     "psnr_outer_only_px": round(psnr_of(rgb, regions["outer_only_px"]), 2)}
+    return out
+
+
 def main():
     import argparse
     ap = argparse.ArgumentParser()
     ap.add_argument("--iters", type=int, default=300)
     ap.add_argument("--adapt-every", type=int, default=50)
+    ap.add_argument("--pruning-study", action="store_true",
+                    help="only the static pruning comparison on the layered scene")
     args = ap.parse_args()
     ctx = lv.Context(0)
+    if args.pruning_study:
+        print(json.dumps(pruning_study(ctx)), flush=True)
+        ctx.close()
+        return
     out = {"problem": "synthetic shell, 60k leaves (SH1), 6 views 192x144; start: 32^3 grid"}
     # the plain per-bin quantile of eq. 12 is the guarded step with neutral
     # guards: alpha 1, one threshold, no halo, no cap

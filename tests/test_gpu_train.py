@@ -113,3 +113,18 @@ def test_training_with_aux_terms_runs(ctx):
     assert res["final_loss"] < 0.8 * res["first_loss"]
     assert torch.isfinite(t.density).all() and torch.isfinite(t.sh).all()
     assert len(res["adapt"]) == 1
+
+
+def test_pruning_study_spreads_pruning_over_depth(ctx):
+    """Pruning alone on the layered scene: the per-bin depth quantile takes
+    the same share from every depth range, so it keeps more of the
+    semi-transparent outer shell (whose low weights a global threshold
+    removes first) at about the same voxel count."""
+    from paper_2511_02510_amd import train
+    res = train.pruning_study(ctx, q=0.2, rounds=3)
+    say(f"  pruning study: {res}")
+    g, d = res["global"], res["depth_quantile"]
+    assert abs(g["voxels"] - d["voxels"]) <= 0.05 * g["voxels"]
+    assert d["outer"] > g["outer"] and d["inner"] < g["inner"]
+    for r in (g, d):
+        assert r["inner"] + r["outer"] == r["voxels"] and r["psnr"] > 30.0
