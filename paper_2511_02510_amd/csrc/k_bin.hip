@@ -257,6 +257,8 @@ __global__ __launch_bounds__(kBinBlock) void k_preprocess(RasterArgs a) {
     const float R3 = cam.R[3], R4 = cam.R[4], R5 = cam.R[5];
     const float R6 = cam.R[6], R7 = cam.R[7], R8 = cam.R[8];
     const float o0 = cam.o[0], o1 = cam.o[1], o2 = cam.o[2];
+    // read once per view: inside the corners' branches each read is a load
+    const float cfx = cam.fx, cfy = cam.fy, ccx = cam.cx, ccy = cam.cy;
     const int W = cam.width, H = cam.height;
     // --- binary32 projection of the 8 corners (no contraction, fixed order)
     float u0 = INFINITY, u1 = -INFINITY, v0 = INFINITY, v1 = -INFINITY;
@@ -278,8 +280,8 @@ __global__ __launch_bounds__(kBinBlock) void k_preprocess(RasterArgs a) {
       } else {
         const Divisor dz = divisor(zc);
         const float qx = quotient(xc, dz), qy = quotient(yc, dz);
-        const float uu = cam.fx * qx + cam.cx;
-        const float vv = cam.fy * qy + cam.cy;
+        const float uu = cfx * qx + ccx;
+        const float vv = cfy * qy + ccy;
         u0 = fminf(u0, uu); u1 = fmaxf(u1, uu);
         v0 = fminf(v0, vv); v1 = fmaxf(v1, vv);
       }

@@ -28,8 +28,11 @@ constexpr int kCounterWords = 128 + 2 * kQueues * kQueueStride;
 constexpr int kSpread = 16;
 constexpr int kBinBlock = 256;   // voxels per block of preprocess and emit
 // a block counts the tiles its records cover in an LDS table over the
-// block's tile bounding box when that box has at most kTileWin tiles
-constexpr int kTileWin = 2048;
+// block's tile bounding box when that box has at most kTileWin tiles (512:
+// the emit's tables then take 6 KB, so more of its workgroups fit a CU; on
+// the ring workload 2048 was 10 us slower, 256 sent too many blocks down
+// the per-record path)
+constexpr int kTileWin = 512;
 
 // per-view table built on the device from the cameras (graph-replay safe)
 struct ViewTab {
