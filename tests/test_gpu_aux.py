@@ -74,11 +74,13 @@ def test_aux_channels_forward(ctx, tile, chunk):
         assert torch.equal(t, out[k]), k
 
 
-@pytest.mark.parametrize("which", ["all", "dist", "normal"])
-def test_aux_backward_matches_oracle(ctx, which):
+@pytest.mark.parametrize("which,tile,chunk", [("all", 16, 64), ("dist", 16, 64),
+                                              ("normal", 16, 64), ("all", 8, 256),
+                                              ("all", 32, 128)])
+def test_aux_backward_matches_oracle(ctx, which, tile, chunk):
     import torch
     sc, cams = _scene()
-    r, vox, frame, out = _render(ctx, sc, cams, 16, 64)
+    r, vox, frame, out = _render(ctx, sc, cams, tile, chunk)
     P = frame.P
     rng = np.random.default_rng(82)
     g_rgb = rng.normal(0, 1e-3, 3 * P)
@@ -97,7 +99,8 @@ def test_aux_backward_matches_oracle(ctx, which):
     # the auxiliary part alone
     dd0, dsh0 = oracle.backward(sc, cams, g_rgb, g_depth, g_alpha)
     e_aux = rel_l2(_np(dd) - dd0, dd_ref - dd0)
-    say(f"  aux backward [{which}]: gradient rel-L2 {e:.2e}, density part of the aux terms {e_aux:.2e}")
+    say(f"  aux backward [{which}, tile {tile} chunk {chunk}]: gradient rel-L2 {e:.2e}, "
+        f"density part of the aux terms {e_aux:.2e}")
     assert e <= GRAD_TOL and e_aux <= GRAD_TOL
 
 
@@ -266,6 +269,24 @@ def test_aux_grid_layout_softplus(ctx):
     e1, e2 = rel_l2(dd, dd_ref), rel_l2(dsh, dsh_ref)
     say(f"  gradient rel-L2 grid values {e1:.2e} sh {e2:.2e}")
     assert e1 <= GRAD_TOL and e2 <= GRAD_TOL
+
+
+def test_aux_channels_of_an_empty_scene(ctx):
+    """No voxel in front of the camera: both channels are 0 and the
+    backward gives zero gradients."""
+    import torch
+    import paper_2511_02510_amd as lv
+    sc, _ = _scene()
+    cams = [look_at((0.0, 0.0, 3.0), 40, 30, target=(0.0, 0.0, 9.0))]   # looking away
+    r, vox, frame, out = _render(ctx, sc, cams, 16, 64)
+    assert float(out["dist"].abs().max()) == 0.0 and float(out["normal"].abs().max()) == 0.0
+    assert float(out["alpha"].abs().max()) == 0.0
+    P = frame.P
+    dd, dsh = torch.empty_like(vox.density), torch.empty_like(vox.sh)
+    ones = lambda n: torch.ones(n, device=ctx.device)
+    r.backward_aux(ones(3 * P), ones(P), ones(P), out["depth"], ones(P), ones(3 * P), dd, dsh)
+    torch.cuda.synchronize()
+    assert float(dd.abs().max()) == 0.0 and float(dsh.abs().max()) == 0.0
 
 
 def test_aux_argument_errors(ctx):
