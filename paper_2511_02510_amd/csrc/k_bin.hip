@@ -125,6 +125,29 @@ struct TileWin {
   bool any;
 };
 
+// Wave-wide min / max with DPP row shifts and row broadcasts (an inclusive
+// scan whose last lane holds the result, read back by every lane); every
+// lane of the wave must be active.
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) {
+  const int id = -1;   // 0xFFFFFFFF: the identity of the unsigned min
+  x = min(x, uint32_t(__builtin_amdgcn_update_dpp(id, int(x), 0x111, 0xf, 0xf, false)));
+  x = min(x, uint32_t(__builtin_amdgcn_update_dpp(id, int(x), 0x112, 0xf, 0xf, false)));
+  x = min(x, uint32_t(__builtin_amdgcn_update_dpp(id, int(x), 0x114, 0xf, 0xf, false)));
+  x = min(x, uint32_t(__builtin_amdgcn_update_dpp(id, int(x), 0x118, 0xf, 0xf, false)));
+  x = min(x, uint32_t(__builtin_amdgcn_update_dpp(id, int(x), 0x142, 0xa, 0xf, false)));
+  x = min(x, uint32_t(__builtin_amdgcn_update_dpp(id, int(x), 0x143, 0xc, 0xf, false)));
+  return uint32_t(__builtin_amdgcn_readlane(int(x), 63));
+}
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
+  x = max(x, uint32_t(__builtin_amdgcn_update_dpp(0, int(x), 0x111, 0xf, 0xf, false)));
+  x = max(x, uint32_t(__builtin_amdgcn_update_dpp(0, int(x), 0x112, 0xf, 0xf, false)));
+  x = max(x, uint32_t(__builtin_amdgcn_update_dpp(0, int(x), 0x114, 0xf, 0xf, false)));
+  x = max(x, uint32_t(__builtin_amdgcn_update_dpp(0, int(x), 0x118, 0xf, 0xf, false)));
+  x = max(x, uint32_t(__builtin_amdgcn_update_dpp(0, int(x), 0x142, 0xa, 0xf, false)));
+  x = max(x, uint32_t(__builtin_amdgcn_update_dpp(0, int(x), 0x143, 0xc, 0xf, false)));
+  return uint32_t(__builtin_amdgcn_readlane(int(x), 63));
+}
+
 // Bounding box of the tiles covered by the block's records; every thread of
 // the block must call it (have: the thread's record covers [tx0, tx1] x
 // [ty0, ty1]).
@@ -133,13 +156,10 @@ __device__ TileWin block_tile_window(bool have, uint32_t tx0, uint32_t tx1, uint
   __shared__ uint32_t s_r[kBinBlock / 64][4];
   uint32_t a0 = have ? tx0 : 0xFFFFFFFFu, a1 = have ? tx1 : 0u;
   uint32_t b0 = have ? ty0 : 0xFFFFFFFFu, b1 = have ? ty1 : 0u;
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    a0 = min(a0, uint32_t(__shfl_xor(int(a0), o, 64)));
-    a1 = max(a1, uint32_t(__shfl_xor(int(a1), o, 64)));
-    b0 = min(b0, uint32_t(__shfl_xor(int(b0), o, 64)));
-    b1 = max(b1, uint32_t(__shfl_xor(int(b1), o, 64)));
-  }
+  a0 = wave_min_u32(a0);
+  a1 = wave_max_u32(a1);
+  b0 = wave_min_u32(b0);
+  b1 = wave_max_u32(b1);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   if (lane == 0) {
     s_r[w][0] = a0; s_r[w][1] = a1; s_r[w][2] = b0; s_r[w][3] = b1;
