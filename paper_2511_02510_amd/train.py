@@ -13,9 +13,10 @@ gradients join the photometric one in a single backward.
 Every per-pixel and per-voxel step of the method is a library call; PyTorch
 holds the tensors, runs Adam and gathers the kept voxels.  A global-threshold
 pruning mode (prune w_max <= the nearest-rank q-quantile over all voxels, no
-guards) is the baseline for the peak-VRAM comparison.
+guards) and subdivision without any pruning are the baselines for the
+peak-VRAM comparison.
 
-    python -m paper_2511_02510_amd.train   # global / per-bin / guarded pruning, one JSON line
+    python -m paper_2511_02510_amd.train   # none / global / per-bin / guarded pruning, one JSON line
 """
 from __future__ import annotations
 
@@ -43,7 +44,7 @@ class TrainConfig:
     t1_frac: float = 0.6
     form: int = 0                   # eq. 7
     eps: float = 1e-3
-    prune: str = "depth_quantile"   # or "global"
+    prune: str = "depth_quantile"   # or "global", or "none" (subdivision only)
     n_bins: int = 16
     q: float = 0.1
     guard: Dict[str, float] = dataclasses.field(default_factory=dict)
@@ -161,6 +162,8 @@ class Trainer:
             k = min(max(int(math.ceil(c.q * n)), 1), n)
             thr = torch.kthvalue(self.wmax, k).values
             prune = (self.wmax <= thr).to(torch.uint8)
+        elif c.prune == "none":
+            prune.zero_()
         else:
             raise ValueError(f"unknown pruning mode {c.prune}")
         keep = prune == 0
@@ -368,7 +371,8 @@ def main():
     # the plain per-bin quantile of eq. 12 is the guarded step with neutral
     # guards: alpha 1, one threshold, no halo, no cap
     neutral = dict(alpha=1.0, m_low=0.5, m_high=0.5, rho=0.0, w_keep=2.0, cap_frac=1.0)
-    runs = {"global_threshold": dict(prune="global"),
+    runs = {"no_pruning": dict(prune="none"),
+            "global_threshold": dict(prune="global"),
             "depth_quantile": dict(prune="depth_quantile", guard=neutral),
             "depth_quantile_guards": dict(prune="depth_quantile")}
     for name, kw in runs.items():

@@ -128,3 +128,23 @@ def test_pruning_study_spreads_pruning_over_depth(ctx):
     assert d["outer"] > g["outer"] and d["inner"] < g["inner"]
     for r in (g, d):
         assert r["inner"] + r["outer"] == r["voxels"] and r["psnr"] > 30.0
+
+
+def test_pruning_bounds_voxels_and_peak_memory(ctx):
+    """Subdivision alone against subdivision with the per-bin pruning (the
+    paper's pruning ablation, Sec. V): pruning ends with fewer voxels and a
+    lower peak of allocated device memory."""
+    from paper_2511_02510_amd import train
+    out = {}
+    neutral = dict(alpha=1.0, m_low=0.5, m_high=0.5, rho=0.0, w_keep=2.0, cap_frac=1.0)
+    for mode, kw in (("none", dict(prune="none")),
+                     ("depth_quantile", dict(prune="depth_quantile", guard=neutral))):
+        vox, frame, target, _, _ = train.training_problem(ctx, n_gt=20000, views=3,
+                                                          res=(96, 72), init_level=4, seed=9)
+        cfg = train.TrainConfig(iters=90, adapt_every=30, q=0.2, split=dict(max_splits=2000), **kw)
+        out[mode] = train.Trainer(ctx, vox, frame, target, cfg).run()
+        say(f"  {mode}: voxels {out[mode]['voxels']}, peak {out[mode]['peak_vram_mb']} MB, "
+            f"PSNR {out[mode]['final_psnr']:.2f}")
+    assert out["depth_quantile"]["voxels"] < out["none"]["voxels"]
+    assert out["depth_quantile"]["peak_vram_mb"] < out["none"]["peak_vram_mb"]
+    assert all(a["pruned"] == 0 for a in out["none"]["adapt"])
