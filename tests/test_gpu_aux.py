@@ -271,6 +271,26 @@ def test_aux_grid_layout_softplus(ctx):
     assert e1 <= GRAD_TOL and e2 <= GRAD_TOL
 
 
+def test_aux_forward_with_one_channel(ctx):
+    """Either channel may be omitted: the other one and the plain outputs are
+    those of the call with both."""
+    import torch
+    sc, cams = _scene()
+    r, vox, frame, out = _render(ctx, sc, cams, 16, 64)
+    P = frame.P
+    for keep in ("dist", "normal"):
+        rgb, depth, alpha = r.new_outputs()
+        wm = torch.zeros(vox.n, device=ctx.device)
+        d = torch.full((P,), 7.0, device=ctx.device) if keep == "dist" else None
+        n = torch.full((3 * P,), 7.0, device=ctx.device) if keep == "normal" else None
+        r.forward(rgb, depth, alpha, wm, dist=d, normal=n)
+        torch.cuda.synchronize()
+        got = d if keep == "dist" else n
+        assert torch.equal(got, out[keep]), keep
+        for k, t in (("rgb", rgb), ("depth", depth), ("alpha", alpha), ("wmax", wm)):
+            assert torch.equal(t, out[k]), (keep, k)
+
+
 def test_aux_channels_of_an_empty_scene(ctx):
     """No voxel in front of the camera: both channels are 0 and the
     backward gives zero gradients."""
