@@ -81,3 +81,19 @@ def test_leaves_are_stored_in_octree_order():
             prev = t
     g, _, _ = synth.make_config("grid4k")
     assert g.ijk[:, 1].tolist() == [1, 0, 0] and g.ijk[:, 2].tolist() == [0, 1, 0]
+
+
+def test_layered_scene_of_the_pruning_study():
+    """The two shells of the pruning study form one overlap-free leaf set in
+    octree order; the tag marks the outer shell's leaves and the inner
+    shell is the denser one."""
+    from paper_2511_02510_amd.train import layered_scene
+    sc, outer, inner_sc, outer_sc = layered_scene()
+    assert sc.n == inner_sc.n + outer_sc.n == 50000 and int(outer.sum()) == outer_sc.n
+    _assert_no_overlap(sc)
+    e = sc.root_size * np.exp2(-sc.level.astype(np.float64))
+    r = np.linalg.norm(sc.root_min[:, None] + (sc.ijk + 0.5) * e, axis=0)
+    assert r[~outer].max() < r[outer].min()
+    assert np.median(sc.density[:, ~outer]) > 10 * np.median(sc.density[:, outer])
+    order = synth.scenes.octree_order(sc.ijk, sc.level)
+    assert np.array_equal(order, np.arange(sc.n))
