@@ -325,3 +325,64 @@ def test_aux_argument_errors(ctx):
     with pytest.raises(lv.LiteVoxelError):   # every pointer of lv_aux_loss is required
         lv.aux_loss(ctx, frame, out["depth"], out["alpha"], out["normal"], out["dist"], 1.0, 1.0,
                     1.0, loss, bufs[0], None, bufs[2], bufs[3])
+
+
+def test_aux_step_graph_replays_match_eager(ctx):
+    """forward with both channels, the three terms and the backward with
+    every channel's gradient, captured once: replays (with eager work between
+    them) equal the eager step; the channels bit for bit, the summed losses
+    and the gradients up to the order of their atomic sums."""
+    import torch
+    import paper_2511_02510_amd as lv
+    sc, cams = _scene()
+    dev = ctx.device
+    vox = lv.Voxels.from_scene(sc, dev)
+    frame = lv.Frame(cams, dev)
+    r = lv.Renderer(ctx, vox, frame, lv.settings(tile=16, chunk=128, chunk_bwd=64))
+    P, V = frame.P, frame.n_views
+    rgb, depth, alpha = r.new_outputs()
+    dist, normal = torch.empty(P, device=dev), torch.empty(3 * P, device=dev)
+    wmax = torch.zeros(vox.n, device=dev)
+    loss = torch.empty(3 * V, device=dev)
+    ga, gd, gl = (torch.empty(P, device=dev) for _ in range(3))
+    gn = torch.empty(3 * P, device=dev)
+    d_rgb = to_dev(np.random.default_rng(90).normal(0, 1e-3, 3 * P), dev)
+    dd, dsh = torch.empty_like(vox.density), torch.empty_like(vox.sh)
+    stream = torch.cuda.Stream()
+
+    def step():
+        wmax.zero_()
+        r.forward(rgb, depth, alpha, wmax, stream=stream, verify=False, dist=dist, normal=normal)
+        lv.aux_loss(ctx, frame, depth, alpha, normal, dist, 0.05, 0.2, 5.0, loss, ga, gd, gn, gl,
+                    stream=stream)
+        r.backward_aux(d_rgb, gd, ga, depth, gl, gn, dd, dsh, stream=stream)
+
+    def snap():
+        torch.cuda.synchronize()
+        return [x.clone() for x in (rgb, depth, alpha, dist, normal, wmax, ga, gd, gn, gl, loss,
+                                    dd, dsh)]
+
+    say("auxiliary step: graph capture and replays")
+    with torch.cuda.stream(stream):
+        r.forward(rgb, depth, alpha, wmax, stream=stream, verify=True)   # sizes the capacity
+        step()
+    eager = snap()
+    with torch.cuda.stream(stream):
+        lv.graph_begin(ctx, stream)
+        step()
+        lv.graph_end(ctx, stream)
+    try:
+        for rep in range(3):
+            for x in (rgb, dist, normal, gd, dd):
+                x.fill_(-7.0)
+            torch.cuda.synchronize()
+            lv.graph_launch(ctx, stream)
+            got = snap()
+            for a, b in zip(got[:10], eager[:10]):      # channels, w_max, image gradients
+                assert torch.equal(a, b), f"replay {rep}"
+            assert torch.allclose(got[10], eager[10], rtol=1e-5, atol=1e-9), f"replay {rep}"
+            for a, b in zip(got[11:], eager[11:]):
+                assert rel_l2(a.cpu().numpy(), b.cpu().numpy()) < 1e-5, f"replay {rep}"
+            _ = (torch.randn(1000, device=dev) * 2).sum().item()     # eager work between replays
+    finally:
+        lv.graph_reset(ctx)
