@@ -8,8 +8,8 @@ Parts and the passages they follow:
                   analytic adjoint of eq. 2-4 (ref_backward)
                   binary32 binning + visibility code (key path)
   raster_ref.cpp  auxiliary channels (ref_render_aux,           eq. 6, 17 (named
-                  ref_backward_aux): distortion, normal        terms; readings
-                                                               in the file)
+                  ref_backward_aux): distortion, normal;       terms; readings
+                  median depth (ref_median_depth)              in the file)
   aux.py          transmittance concentration, depth-normal
                   consistency, distortion mean (image terms)   eq. 6, 17
   loss.py         inverse-Sobel weight, mean normalisation,
@@ -71,6 +71,8 @@ def lib():
         L.ref_backward_aux.argtypes = [i64, i32, P, f64, P, P, P, P, i32, P, P, P,
                                        P, P, P, P, P, P, P, i32]
         L.ref_backward_aux.restype = i32
+        L.ref_median_depth.argtypes = [i64, i32, P, f64, P, P, P, P, i32, P, P, f64, P, i32]
+        L.ref_median_depth.restype = i32
         L.ref_footprint_pixels.argtypes = [i64, P, f64, P, P, i32, P, P, P, i64, P, i64]
         L.ref_footprint_pixels.restype = i64
         L.ref_voxel_colours.argtypes = [i64, i32, P, f64, P, P, P, i32, P, P, P, P]
@@ -201,6 +203,18 @@ def render_aux(scene, cams, bg=(0.0, 0.0, 0.0), wmax_in=None, threads=0):
                          _p(alpha), _p(dist), _p(normal), _p(wmax), int(threads))
     return dict(rgb=rgb, views=split_views(rgb, cams), depth=depth, alpha=alpha, dist=dist,
                 normal=normal, wmax=wmax)
+
+
+def median_depth(scene, cams, t_half=0.5, threads=0):
+    """FP64 median depth [P]: chord midpoint of the first hit after which the
+    transmittance is at most t_half (0 where none is); see raster_ref.cpp."""
+    S = _SceneArrays(scene)
+    c, wh = cams_arrays(cams)
+    P = int(pix_offsets(cams)[-1])
+    md = np.zeros(P, dtype=np.float64)
+    lib().ref_median_depth(*S.args(), len(cams), _p(c), _p(wh), float(t_half), _p(md),
+                           int(threads))
+    return md
 
 
 def backward_aux(scene, cams, g_rgb, g_depth=None, g_alpha=None, g_dist=None, g_normal=None,

@@ -17,6 +17,12 @@ the caller):
       m = (e_y x e_x) / |e_y x e_x| (0 when the cross product vanishes),
       which faces the camera for a visible surface.  Since |N| <= A,
       L_n >= 0, with 0 when every blended voxel normal equals m.
+  median depth-normal consistency (eq. 17's median-based variant)
+                               L_nm = 1/|I| sum_{p in I} (A_p - N_p . m'_p)
+      with m' the normal of the median-depth map M (the chord midpoint of the
+      first hit after which the transmittance is at most 1/2, 0 where none
+      is): the same stencil on M instead of D.  M is piecewise constant in
+      the densities, so the term passes no depth gradient.
 """
 from __future__ import annotations
 
@@ -47,15 +53,18 @@ def depth_normals(depth: np.ndarray, cam):
     return m, c, ln, d
 
 
-def aux_losses(depth, alpha, normal, dist, cams, lam_tc=1.0, lam_n=1.0, lam_d=1.0):
-    """Per-view losses [V, 3] (L_Tc, L_n, L_d, each times its weight) and the
-    gradients of their sum: g_alpha [P], g_depth [P], g_normal [3P] (rgb
-    layout), g_dist [P]."""
+def aux_losses(depth, alpha, normal, dist, cams, lam_tc=1.0, lam_n=1.0, lam_d=1.0, mdepth=None,
+               lam_nm=0.0):
+    """Per-view losses [V, 4] (L_Tc, L_n, L_d, L_nm, each times its weight;
+    L_nm is 0 without mdepth) and the gradients of their sum: g_alpha [P],
+    g_depth [P], g_normal [3P] (rgb layout), g_dist [P]."""
     off = pix_offsets(cams)
     P = int(off[-1])
     depth, alpha, dist = (np.asarray(a, np.float64).ravel() for a in (depth, alpha, dist))
     normal = np.asarray(normal, np.float64).ravel()
-    losses = np.zeros((len(cams), 3))
+    losses = np.zeros((len(cams), 4))
+    if mdepth is not None:
+        mdepth = np.asarray(mdepth, np.float64).ravel()
     g_alpha, g_depth, g_dist = np.zeros(P), np.zeros(P), np.zeros(P)
     g_normal = np.zeros(3 * P)
     for v, cam in enumerate(cams):
@@ -94,6 +103,11 @@ def aux_losses(depth, alpha, normal, dist, cams, lam_tc=1.0, lam_n=1.0, lam_d=1.
             gX[2:, 1:-1] += gey
             gX[:-2, 1:-1] -= gey
             gd = np.sum(gX * pixel_dirs(cam), -1)
+            if mdepth is not None:
+                mm, _, _, _ = depth_normals(mdepth[sl].reshape(H, W), cam)
+                losses[v, 3] = lam_nm * float(np.sum(Ai - np.sum(Ni * mm, -1))) / ni
+                ga[1:-1, 1:-1] += lam_nm / ni
+                gn[1:-1, 1:-1] += -lam_nm * mm / ni
         g_alpha[sl] = ga.ravel()
         g_depth[sl] = gd.ravel()
         g_normal[3 * int(off[v]):3 * int(off[v + 1])] = gn.transpose(2, 0, 1).ravel()

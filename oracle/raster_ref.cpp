@@ -471,6 +471,43 @@ int ref_render_aux(int64_t n, int deg, const float* root_min, double root_size,
   return 0;
 }
 
+// Median depth per pixel (the depth the median-based depth-normal term of
+// eq. 17 reads; reading): the chord midpoint of the first hit after which the
+// transmittance is at most t_half (1/2: half the opacity accumulated), 0 when
+// no hit takes it there.  It moves only when the crossing jumps to another
+// hit, so it passes no gradient to the densities.
+int ref_median_depth(int64_t n, int deg, const float* root_min, double root_size,
+                     const uint16_t* ijk, const uint8_t* level, const double* density,
+                     const double* sh, int n_views, const float* cams, const int32_t* wh,
+                     double t_half, double* mdepth, int n_threads) {
+  Scene sc = make_scene(n, deg, root_min, root_size, ijk, level, density, sh);
+  auto C = load_cams(n_views, cams, wh);
+  auto off = pix_offsets(C);
+  std::vector<ViewBins> bins(n_views);
+  for (int i = 0; i < n_views; ++i) bins[i] = bin_view(sc, C[i]);
+  int64_t total = off[n_views];
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel
+  {
+    std::vector<Hit> hits;
+    std::vector<double> w, tm, len, Ta;
+#pragma omp for schedule(dynamic, 256)
+    for (int64_t g = 0; g < total; ++g) {
+      PixLoc pl = locate(off, C, g);
+      trace(sc, C[pl.view], bins[pl.view], pl.px, pl.py, hits, false);
+      hit_weights(hits, w, tm, len, Ta);
+      double md = 0.0;
+      for (size_t k = 0; k < hits.size(); ++k)
+        if (Ta[k] <= t_half) {
+          md = tm[k];
+          break;
+        }
+      mdepth[g] = md;
+    }
+  }
+  return 0;
+}
+
 // Analytic gradient with the auxiliary channels.  Upstream per pixel:
 // g_rgb (rgb layout), g_depth, g_alpha, g_dist [P], g_normal (rgb layout);
 // every pointer but g_rgb may be NULL.  With G_k = dL/dw_k (colour, depth,

@@ -210,3 +210,71 @@ def test_aux_losses_gradients_by_finite_differences():
             xs[arr][i] -= 2 * h
             lm = tot(xs["D"], xs["A"], xs["N"], xs["l"])
             assert abs((lp - lm) / (2 * h) - g[i]) < 1e-7 * max(1.0, abs(g[i])), (arr, i)
+
+
+# ------------------------------------------------------------ median depth
+def test_median_depth_single_voxel_either_side_of_one_half():
+    # constant density sigma over a chord of length 1: T = exp(-sigma); half
+    # the opacity is reached exactly when sigma >= ln 2
+    cam = axis_camera((0.0, 0.0, -3.0), (0.0, 0.0, 0.0))
+    k = 32 * 65 + 32
+    for sigma, want in ((math.log(2.0) + 0.01, 3.0), (math.log(2.0) - 0.01, 0.0)):
+        s = float(np.float32(sigma))
+        sc = one_voxel_scene(s, (0.5, 0.5, 0.5))
+        md = oracle.median_depth(sc, [cam])
+        assert abs(md[k] - want) < 1e-12, (sigma, md[k])
+    # a pixel that misses the voxel has no median depth
+    assert md[0] == 0.0
+
+
+def test_median_depth_two_voxels_picks_the_crossing_hit():
+    g = GOLDEN["two_voxel_stack"]
+    cam = axis_camera((-0.5, -0.5, -4.0), (-0.5, -0.5, 0.0))
+    k = 32 * 65 + 32
+    # exp(-0.4) > 1/2 > exp(-0.9): the second hit takes T below one half;
+    # exp(-0.8) < 1/2: the first one does
+    for s1, s2, want in ((0.4, 0.5, g["t_mid2"]), (0.8, 0.5, g["t_mid1"]), (0.2, 0.3, 0.0)):
+        sc = Scene(root_min=np.array([-1, -1, -1], np.float32), root_size=2.0,
+                   ijk=np.array([[0, 0], [0, 0], [0, 1]], np.uint16),
+                   level=np.array([1, 1], np.uint8),
+                   density=np.array([[s1, s2]] * 8, np.float32),
+                   sh=np.full((3, 2), 0.5, np.float32), sh_degree=0)
+        assert abs(oracle.median_depth(sc, [cam])[k] - want) < 1e-12, (s1, s2)
+
+
+def test_median_depth_normal_term_is_the_mean_term_on_the_same_map():
+    """With the median-depth map equal to the depth map, the median term is
+    the mean term (its weight swapped) with the same alpha and normal
+    gradients; it passes no depth gradient."""
+    cams = [look_at((0.3, 0.4, -2.5), 9, 7), look_at((2.0, 0.1, 0.5), 6, 5)]
+    P = sum(c.npix for c in cams)
+    rng = np.random.default_rng(12)
+    D = np.concatenate([_plane_depth(c, (0, 0, 0), (0.2, -0.3, -1.0))[0].ravel() for c in cams])
+    D = D + rng.normal(0, 0.05, P)
+    A = rng.uniform(0.2, 0.9, P)
+    N = rng.normal(0, 0.3, 3 * P)
+    dist = np.zeros(P)
+    Ln, ga_n, gd_n, gn_n, _ = aux.aux_losses(D, A, N, dist, cams, 0.0, 0.8, 0.0)
+    Lm, ga_m, gd_m, gn_m, _ = aux.aux_losses(D, A, N, dist, cams, 0.0, 0.0, 0.0, mdepth=D,
+                                             lam_nm=0.8)
+    assert np.allclose(Lm[:, 3], Ln[:, 1], rtol=1e-14, atol=0.0)
+    assert np.all(Lm[:, :3] == 0.0)
+    assert np.allclose(ga_m, ga_n, rtol=1e-14, atol=0.0)
+    assert np.allclose(gn_m, gn_n, rtol=1e-14, atol=0.0)
+    assert np.all(gd_m == 0.0) and np.any(gd_n != 0.0)
+    # finite differences in alpha and normal of the median term alone
+    M = D + rng.normal(0, 0.02, P)
+    _, ga, _, gn, _ = aux.aux_losses(D, A, N, dist, cams, 0.0, 0.0, 0.0, mdepth=M, lam_nm=1.7)
+    tot = lambda A_, N_: float(np.sum(aux.aux_losses(D, A_, N_, dist, cams, 0.0, 0.0, 0.0,
+                                                     mdepth=M, lam_nm=1.7)[0]))
+    h = 1e-6
+    for i in rng.integers(0, P, 10):
+        Ap, Am = A.copy(), A.copy()
+        Ap[i] += h
+        Am[i] -= h
+        assert abs((tot(Ap, N) - tot(Am, N)) / (2 * h) - ga[i]) < 1e-7
+    for i in rng.integers(0, 3 * P, 20):
+        Np, Nm = N.copy(), N.copy()
+        Np[i] += h
+        Nm[i] -= h
+        assert abs((tot(A, Np) - tot(A, Nm)) / (2 * h) - gn[i]) < 1e-7
