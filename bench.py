@@ -322,20 +322,21 @@ def main():
     log(f"[bench] pairs Q={Q} capacity={r.st.pair_capacity}")
 
     # buffers of the step with the auxiliary channels and terms: forward with
-    # the distortion and normal channels, loss weight, L1, the three
-    # auxiliary terms, one backward taking every channel's gradient
+    # the distortion, normal and median-depth channels, loss weight, L1, the
+    # four auxiliary terms, one backward taking every channel's gradient
     dist_c, normal_c = torch.empty(P, device=dev), torch.empty(3 * P, device=dev)
-    aloss = torch.empty(3 * len(cams), device=dev)
+    mdepth_c = torch.empty(P, device=dev)
+    aloss = torch.empty(4 * len(cams), device=dev)
     ga_c, gd_c, gl_c = (torch.empty(P, device=dev) for _ in range(3))
     gn_c = torch.empty(3 * P, device=dev)
 
     def aux_step(verify=False):
         lv.lf_weight(ctx, frame, target, gamma, 0, 1e-3, weight, lw_ws, stream=stream)
         r.forward(rgb, depth, alpha, wmax, stream=stream, verify=verify, dist=dist_c,
-                  normal=normal_c)
+                  normal=normal_c, mdepth=mdepth_c)
         lv.l1_grad(ctx, frame, rgb, target, weight, loss, d_rgb, stream=stream)
         lv.aux_loss(ctx, frame, depth, alpha, normal_c, dist_c, 0.01, 0.05, 1.0, aloss, ga_c,
-                    gd_c, gn_c, gl_c, stream=stream)
+                    gd_c, gn_c, gl_c, stream=stream, mdepth=mdepth_c, lam_nm=0.05)
         r.backward_aux(d_rgb, gd_c, ga_c, depth, gl_c, gn_c, d_density, d_sh, stream=stream)
 
     if args.profile_aux_steps > 0:
@@ -510,9 +511,8 @@ def main():
            "apply_hbm_frac": round(per_voxel * (scene.n + n_out) / (t_apply * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     log(f"[bench] subdivision {subdiv}")
 
-    # ---- the auxiliary channels and terms on this workload: forward with the
-    # distortion and normal channels, loss weight, L1, the three auxiliary
-    # terms, one backward taking every channel's gradient
+    # ---- the auxiliary channels and terms on this workload (the step built
+    # above)
     aux_step(verify=True)
     torch.cuda.synchronize()
     lv.set_timing(ctx, True)
@@ -526,7 +526,8 @@ def main():
     # the event and the launch do not count
     t_aux_loss = gpu_ms(lambda: [lv.aux_loss(ctx, frame, depth, alpha, normal_c, dist_c, 0.01,
                                              0.05, 1.0, aloss, ga_c, gd_c, gn_c, gl_c,
-                                             stream=stream) for _ in range(10)],
+                                             stream=stream, mdepth=mdepth_c, lam_nm=0.05)
+                                 for _ in range(10)],
                         max(5, args.steps // 2)) / 10
     lv.graph_begin(ctx, stream)
     aux_step()
@@ -540,7 +541,8 @@ def main():
     torch.cuda.synchronize()
     aux_ms = 1e3 * (time.perf_counter() - ta) / args.steps
     lv.graph_reset(ctx)
-    aux = {"step": "fwd (+ distortion, normal) + lf_weight + l1 + aux terms + bwd (all channels)",
+    aux = {"step": "fwd (+ distortion, normal, median depth) + lf_weight + l1 + 4 aux terms + "
+                   "bwd (all channels)",
            "ms_per_step": round(aux_ms, 4), "mp_s": round(P / aux_ms / 1e3, 2),
            "composite_fwd_ms": round(aphases["composite_fwd"], 4),
            "composite_bwd_ms": round(aphases["composite_bwd"], 4),

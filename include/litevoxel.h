@@ -202,9 +202,13 @@ lv_status lv_backward(lv_context* ctx, const lv_voxels* vox, const lv_frame* fra
  *               over the composited hits (tm = (t_in + t_out)/2, l = t_out - t_in);
  *   normal      per pixel  N = sum_k w_k n_k, rgb layout ([3][H][W] per view),
  *               n_v = -u/|u| with u the gradient of voxel v's trilinear
- *               density at the cell centre (n_v = 0 when u = 0).
- * lv_forward_aux is lv_forward that also writes dist and normal (either may
- * be NULL; the rest as lv_forward, the same `saved` for the backward).
+ *               density at the cell centre (n_v = 0 when u = 0);
+ *   mdepth [P]  per pixel  the median depth that the median-based
+ *               depth-normal term of eq. 17 reads: tm of the first hit after
+ *               which the transmittance is at most 1/2, 0 when no hit takes
+ *               it there.  Piecewise constant in the densities: no gradient.
+ * lv_forward_aux is lv_forward that also writes dist, normal and mdepth (any
+ * may be NULL; the rest as lv_forward, the same `saved` for the backward).
  * lv_backward_aux is lv_backward with the upstream gradients of the new
  * channels: d_dist [P] and d_normal (rgb layout), each nullable; d_dist
  * needs depth_fwd, the depth lv_forward_aux wrote for this pass (the
@@ -213,7 +217,7 @@ lv_status lv_backward(lv_context* ctx, const lv_voxels* vox, const lv_frame* fra
 lv_status lv_forward_aux(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
                          const lv_settings* st, void* workspace, void* saved, float* rgb,
                          float* depth, float* alpha, float* wmax, float* dist, float* normal,
-                         hipStream_t stream);
+                         float* mdepth, hipStream_t stream);
 lv_status lv_backward_aux(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
                           const lv_settings* st, void* workspace, const void* saved,
                           const float* d_rgb, const float* d_depth, const float* d_alpha,
@@ -221,22 +225,27 @@ lv_status lv_backward_aux(lv_context* ctx, const lv_voxels* vox, const lv_frame*
                           float* d_density, float* d_sh, hipStream_t stream);
 
 /* Image-space auxiliary terms per view (eq. 6 and 17; readings used):
- *   loss[3v + 0] = lam_tc / |P_v| sum_p A (1 - A)        (transmittance concentration)
- *   loss[3v + 1] = lam_n / |I_v| sum_{p in I_v} (A - N . m)  (depth-normal consistency)
- *   loss[3v + 2] = lam_d / |P_v| sum_p dist              (distortion)
+ *   loss[4v + 0] = lam_tc / |P_v| sum_p A (1 - A)        (transmittance concentration)
+ *   loss[4v + 1] = lam_n / |I_v| sum_{p in I_v} (A - N . m)  (depth-normal consistency)
+ *   loss[4v + 2] = lam_d / |P_v| sum_p dist              (distortion)
+ *   loss[4v + 3] = lam_nm / |I_v| sum_{p in I_v} (A - N . m') (median depth-normal)
  * with I_v the interior pixels (1 <= x <= W-2, 1 <= y <= H-2; none when W or
  * H < 3) and m the unit normal of the surface of the depth channel: X = o +
  * D d (d the pixel's unit ray), m = normalise((X(x,y+1) - X(x,y-1)) x
  * (X(x+1,y) - X(x-1,y))) (0 when the cross product's squared length is below
- * the smallest normal float), facing the camera.  Writes (overwrites) loss
- * [3 n_views] (device; each term summed with float atomics in no fixed order,
- * so the last bits may vary between calls) and the gradients of the summed
- * losses: d_alpha, d_depth, d_dist [P] and d_normal (rgb layout), which are
- * deterministic.  All pointers non-NULL. */
+ * the smallest normal float), facing the camera; m' is the same on the
+ * median-depth map mdepth (from lv_forward_aux), which passes no gradient.
+ * Writes (overwrites) loss [4 n_views] (device; each term summed with float
+ * atomics in no fixed order, so the last bits may vary between calls) and the
+ * gradients of the summed losses: d_alpha, d_depth, d_dist [P] and d_normal
+ * (rgb layout), which are deterministic.  Every pointer but mdepth must be
+ * non-NULL; mdepth may be NULL when lam_nm is 0 (the median term is then 0),
+ * else LV_ERR_ARG. */
 lv_status lv_aux_loss(lv_context* ctx, const lv_frame* frame, const float* depth,
-                      const float* alpha, const float* normal, const float* dist, float lam_tc,
-                      float lam_n, float lam_d, float* loss, float* d_alpha, float* d_depth,
-                      float* d_normal, float* d_dist, hipStream_t stream);
+                      const float* alpha, const float* normal, const float* dist,
+                      const float* mdepth, float lam_tc, float lam_n, float lam_d, float lam_nm,
+                      float* loss, float* d_alpha, float* d_depth, float* d_normal, float* d_dist,
+                      hipStream_t stream);
 
 /* Synchronises the stream and reports the number of (tile, voxel) pairs the
  * forward pass that filled `saved` produced: LV_OK if it fitted,

@@ -68,11 +68,11 @@ _SIGS = {
     "lv_backward": (c_int32, [P, POINTER(LvVoxels), POINTER(LvFrame), POINTER(LvSettings), P, P,
                               P, P, P, P, P, P]),
     "lv_forward_aux": (c_int32, [P, POINTER(LvVoxels), POINTER(LvFrame), POINTER(LvSettings), P, P,
-                                 P, P, P, P, P, P, P]),
+                                 P, P, P, P, P, P, P, P]),
     "lv_backward_aux": (c_int32, [P, POINTER(LvVoxels), POINTER(LvFrame), POINTER(LvSettings), P, P,
                                   P, P, P, P, P, P, P, P, P]),
-    "lv_aux_loss": (c_int32, [P, POINTER(LvFrame), P, P, P, P, c_float, c_float, c_float, P, P, P,
-                              P, P, P]),
+    "lv_aux_loss": (c_int32, [P, POINTER(LvFrame), P, P, P, P, P, c_float, c_float, c_float,
+                              c_float, P, P, P, P, P, P]),
     "lv_check_overflow": (c_int32, [P, POINTER(LvVoxels), POINTER(LvFrame), POINTER(LvSettings),
                                     P, POINTER(c_uint64), P]),
     "lv_pass_stats": (c_int32, [P, POINTER(LvVoxels), POINTER(LvFrame), POINTER(LvSettings), P,

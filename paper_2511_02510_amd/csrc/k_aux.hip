@@ -4,13 +4,15 @@
 //   transmittance concentration  L_Tc = 1/|P| sum_p A_p (1 - A_p)
 //   distortion                   L_d  = 1/|P| sum_p dist_p
 //   depth-normal consistency     L_n  = 1/|I| sum_{p in I} (A_p - N_p . m_p)
+//   median depth-normal          L_nm = 1/|I| sum_{p in I} (A_p - N_p . m'_p)
 // with I the interior pixels (1 <= x <= W-2, 1 <= y <= H-2), N the rendered
 // normal and m the unit normal of the surface the depth channel describes:
 // X_p = o + D_p d_p (d_p the pixel's unit ray), e_x = X(x+1,y) - X(x-1,y),
 // e_y = X(x,y+1) - X(x,y-1), m = (e_y x e_x) / |e_y x e_x| (0 when the
 // cross product vanishes; here, when its squared length is below the smallest
-// normal float), which faces the camera for a visible surface.  Each term is multiplied by
-// its weight.  The depth gradient of a pixel gathers the contributions of
+// normal float), which faces the camera for a visible surface; m' is the same
+// stencil on the median-depth map, which passes no gradient.  Each term is
+// multiplied by its weight.  The depth gradient of a pixel gathers the contributions of
 // the (up to four) interior stencils that read it.
 #include "lv_common.h"
 
@@ -54,10 +56,11 @@ static_assert(kTX * kTY == 256 && kXN <= 512 && kSN <= 512, "two slots per threa
 
 struct AuxLds {
   float X[3][kXN];
+  float X2[3][kXN];   // points of the median-depth map (median instance)
   float m[3][kSN];
   float gex[3][kSN];
   float gey[3][kSN];
-  float part[3][4];
+  float part[4][4];
 };
 
 // prefix of the tile counts over the views: view v owns tiles
@@ -70,11 +73,11 @@ struct AuxView {
   lv_camera c;
   int W, H, ntx;
   size_t npv, pix;   // pixels of the view, offset of its first pixel
-  float inv_p, ni, wn, sc_n, ifx, ify;
+  float inv_p, ni, wn, sc_n, wnm, ifx, ify;
   bool has_int;
 };
 
-__device__ AuxView aux_view(const lv_camera* cams, int v, float lam_n) {
+__device__ AuxView aux_view(const lv_camera* cams, int v, float lam_n, float lam_nm) {
   AuxView u;
   u.c = cams[v];   // a private copy: the kernel's stores cannot alias it
   u.W = u.c.width;
@@ -94,43 +97,48 @@ __device__ AuxView aux_view(const lv_camera* cams, int v, float lam_n) {
   u.inv_p = float(1.0 / double(u.npv));
   u.wn = u.has_int ? lam_n / u.ni : 0.0f;   // weight of each interior pixel's term
   u.sc_n = -u.wn;                           // weight of N . m in the loss
+  u.wnm = u.has_int ? lam_nm / u.ni : 0.0f;  // the median term's per-pixel weight
   u.ifx = 1.0f / u.c.fx;
   u.ify = 1.0f / u.c.fy;
   return u;
 }
 
-// block sum of the three partial terms of view v, weighted, into loss[3 v ..]
-__device__ void aux_flush(AuxLds& L, float p[3], const AuxView& u, int v, float lam_tc,
+// block sum of the four partial terms of view v, weighted, into loss[4 v ..]
+__device__ void aux_flush(AuxLds& L, float p[4], const AuxView& u, int v, float lam_tc,
                           float lam_d, float* loss) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < 4; ++k) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) p[k] += __shfl_xor(p[k], o, 64);
     if (lane == 0) L.part[k][wv] = p[k];
     p[k] = 0.0f;
   }
   __syncthreads();
-  if (threadIdx.x < 3) {
+  if (threadIdx.x < 4) {
     const int k = threadIdx.x;
     const float t = (L.part[k][0] + L.part[k][1]) + (L.part[k][2] + L.part[k][3]);
-    const float f = k == 0 ? lam_tc * u.inv_p : (k == 1 ? u.wn : lam_d * u.inv_p);
-    unsafeAtomicAdd(&loss[3 * v + k], t * f);
+    const float f = k == 0 ? lam_tc * u.inv_p
+                           : (k == 1 ? u.wn : (k == 2 ? lam_d * u.inv_p : u.wnm));
+    unsafeAtomicAdd(&loss[4 * v + k], t * f);
   }
   __syncthreads();
 }
 
+// MED: with the median depth-normal term (mdepth non-null)
+template <bool MED>
 __global__ __launch_bounds__(256) void k_aux_loss(const lv_camera* cams, AuxTiles tl, int V,
                                                   const float* depth, const float* alpha,
                                                   const float* normal, const float* dist,
-                                                  float lam_tc, float lam_n, float lam_d,
-                                                  float* loss, float* g_alpha, float* g_depth,
-                                                  float* g_normal, float* g_dist) {
+                                                  const float* mdepth, float lam_tc, float lam_n,
+                                                  float lam_d, float lam_nm, float* loss,
+                                                  float* g_alpha, float* g_depth, float* g_normal,
+                                                  float* g_dist) {
   __shared__ AuxLds L;
   const uint32_t total = tl.off[V];
   int v = -1;
   AuxView u;
-  float part[3] = {0.0f, 0.0f, 0.0f};
+  float part[4] = {0.0f, 0.0f, 0.0f, 0.0f};
   const int lx = threadIdx.x % kTX, ly = threadIdx.x / kTX;
   // XCD-aware: blocks are dealt to the 8 XCDs round-robin; the blocks of one
   // XCD sweep one contiguous eighth of the tiles, so the halo rows a tile
@@ -146,22 +154,25 @@ __global__ __launch_bounds__(256) void k_aux_loss(const lv_camera* cams, AuxTile
     if (nv != v) {
       if (v >= 0) aux_flush(L, part, u, v, lam_tc, lam_d, loss);
       v = nv;
-      u = aux_view(cams, v, lam_n);
+      u = aux_view(cams, v, lam_n, lam_nm);
     }
     const uint32_t tt = t - tl.off[v];
     const int x0 = int(tt % uint32_t(u.ntx)) * kTX, y0 = int(tt / uint32_t(u.ntx)) * kTY;
     const int W = u.W, H = u.H;
     const size_t npv = u.npv;
     const float* D = depth + u.pix;
+    const float* Dm = MED ? mdepth + u.pix : nullptr;
     const float* N = normal + 3 * u.pix;
     // ---- every load of the tile: depth at two point slots, the rendered
     // normal at two stencil slots and at this thread's pixel, alpha, dist
-    float dep[2], ns[2][3];
+    float dep[2], mdp[2], ns[2][3];
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const int i = threadIdx.x + 256 * j;
       const int gx = x0 - 2 + i % kXW, gy = y0 - 2 + i / kXW;
-      dep[j] = (i < kXN && gx >= 0 && gx < W && gy >= 0 && gy < H) ? D[size_t(gy) * W + gx] : 0.0f;
+      const bool pin = i < kXN && gx >= 0 && gx < W && gy >= 0 && gy < H;
+      dep[j] = pin ? D[size_t(gy) * W + gx] : 0.0f;
+      mdp[j] = (MED && pin) ? Dm[size_t(gy) * W + gx] : 0.0f;
       const int sx = x0 - 1 + i % kSW, sy = y0 - 1 + i / kSW;
       const bool in = i < kSN && sx >= 1 && sx <= W - 2 && sy >= 1 && sy <= H - 2;
 #pragma unroll
@@ -187,7 +198,10 @@ __global__ __launch_bounds__(256) void k_aux_loss(const lv_camera* cams, AuxTile
         float d[3] = {0.0f, 0.0f, 0.0f};
         if (gx >= 0 && gx < W && gy >= 0 && gy < H) aux_ray(u.c, u.ifx, u.ify, gx, gy, d);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) L.X[k][i] = dep[j] * d[k];
+        for (int k = 0; k < 3; ++k) {
+          L.X[k][i] = dep[j] * d[k];
+          if (MED) L.X2[k][i] = mdp[j] * d[k];
+        }
       }
     }
     __syncthreads();
@@ -247,6 +261,26 @@ __global__ __launch_bounds__(256) void k_aux_loss(const lv_camera* cams, AuxTile
         ga += u.wn;
 #pragma unroll
         for (int k = 0; k < 3; ++k) gn[k] = u.sc_n * L.m[k][sc];
+        if (MED) {   // the median map's normal at this pixel: a constant target
+          const int xc = (ly + 2) * kXW + lx + 2;   // this pixel in the point block
+          float ex[3], ey[3], cr[3], mm[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            ex[k] = L.X2[k][xc + 1] - L.X2[k][xc - 1];
+            ey[k] = L.X2[k][xc + kXW] - L.X2[k][xc - kXW];
+          }
+          cross3(ey, ex, cr);
+          const float l2 = cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2];
+          if (l2 >= 1.17549435e-38f) {
+            const float il = __builtin_amdgcn_rsqf(l2);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) mm[k] = cr[k] * il;
+          }
+          part[3] += a - (n0 * mm[0] + n1 * mm[1] + n2 * mm[2]);
+          ga += u.wnm;
+#pragma unroll
+          for (int k = 0; k < 3; ++k) gn[k] -= u.wnm * mm[k];
+        }
       }
       // this pixel is X(x+1) of (x-1, y), X(x-1) of (x+1, y), X(y+1) of
       // (x, y-1) and X(y-1) of (x, y+1); stencils outside the interior are 0
@@ -276,9 +310,9 @@ __global__ void k_aux_zero(float* loss, int n) {
 
 hipError_t run_aux_loss(const lv_camera* cams_host, const lv_camera* cams_dev, int V,
                         const float* depth, const float* alpha, const float* normal,
-                        const float* dist, float lam_tc, float lam_n, float lam_d, float* loss,
-                        float* g_alpha, float* g_depth, float* g_normal, float* g_dist,
-                        hipStream_t s) {
+                        const float* dist, const float* mdepth, float lam_tc, float lam_n,
+                        float lam_d, float lam_nm, float* loss, float* g_alpha, float* g_depth,
+                        float* g_normal, float* g_dist, hipStream_t s) {
   if (V < 1 || V > LV_MAX_VIEWS) return hipErrorInvalidValue;
   AuxTiles tl;
   tl.off[0] = 0;
@@ -289,20 +323,22 @@ hipError_t run_aux_loss(const lv_camera* cams_host, const lv_camera* cams_dev, i
     if (total > 0xffffffffull) return hipErrorInvalidValue;
     tl.off[v + 1] = uint32_t(total);
   }
-  hipLaunchKernelGGL(k_aux_zero, dim3((3 * V + 255) / 256), dim3(256), 0, s, loss, 3 * V);
+  hipLaunchKernelGGL(k_aux_zero, dim3((4 * V + 255) / 256), dim3(256), 0, s, loss, 4 * V);
+  auto kern = mdepth ? k_aux_loss<true> : k_aux_loss<false>;
   // persistent: as many blocks as fit on the device at once
   int dev = 0, cus = 256, per = 1;
   if (hipGetDevice(&dev) == hipSuccess &&
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     cus = 256;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_aux_loss, 256, 0) != hipSuccess ||
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, 256, 0) != hipSuccess ||
       per < 1)
     per = 1;
   uint64_t b = uint64_t(cus) * uint64_t(per);
   if (b > total) b = total;
   if (b < 1) b = 1;
-  hipLaunchKernelGGL(k_aux_loss, dim3(uint32_t(b)), dim3(256), 0, s, cams_dev, tl, V, depth, alpha,
-                     normal, dist, lam_tc, lam_n, lam_d, loss, g_alpha, g_depth, g_normal, g_dist);
+  hipLaunchKernelGGL(kern, dim3(uint32_t(b)), dim3(256), 0, s, cams_dev, tl, V, depth, alpha,
+                     normal, dist, mdepth, lam_tc, lam_n, lam_d, lam_nm, loss, g_alpha, g_depth,
+                     g_normal, g_dist);
   return hipGetLastError();
 }
 

@@ -25,9 +25,10 @@
 // Auxiliary channels (the AUX instances; the training objective's eq. 6 and
 // eq. 17 name the terms they serve without defining them): per pixel the
 // ray-space distortion sum_i sum_j w_i w_j |tm_i - tm_j| + 1/3 sum_i w_i^2 l_i
-// (tm chord midpoint, l chord length) and the rendered normal sum_k w_k n_k
+// (tm chord midpoint, l chord length), the rendered normal sum_k w_k n_k
 // with n_v = -u / |u|, u the gradient of the voxel's trilinear density at
-// the cell centre.  Front to back, the sum of the earlier weights is 1 - T
+// the cell centre, and the median depth (tm of the hit that takes T to 1/2
+// or below, 0 if none does; no gradient passes through it).  Front to back, the sum of the earlier weights is 1 - T
 // and their depth sum is the depth accumulated so far, so the distortion
 // takes one multiply-add chain per hit; the backward recovers the earlier
 // depth sum from the forward's depth.
@@ -390,6 +391,7 @@ struct FwdState {
   float T, C0, C1, C2, D, Tpre;
   uint32_t nlast;
   float N0, N1, N2, L;   // AUX: rendered normal, distortion
+  float M;               // AUX: median depth
 };
 
 // one hit fragment (this lane's pixel, voxel jj at list position pos, chord
@@ -412,6 +414,9 @@ __device__ __forceinline__ float fwd_fragment(const Stage<CH>& S, const StageAux
     st.N0 = fmaf(wk, SA->n[0][jj], st.N0);
     st.N1 = fmaf(wk, SA->n[1][jj], st.N1);
     st.N2 = fmaf(wk, SA->n[2][jj], st.N2);
+    // median depth: the hit that takes the transmittance to 1/2 or below
+    // (T only decreases, so this happens at most once)
+    if (st.T > 0.5f && st.T * ex <= 0.5f) st.M = q.tm;
   }
   st.C0 = fmaf(wk, S.col[0][jj], st.C0);
   st.C1 = fmaf(wk, S.col[1][jj], st.C1);
@@ -475,7 +480,7 @@ __global__ __launch_bounds__(TS* TS) __attribute__((amdgpu_waves_per_eu(6))) voi
     FwdState st;
     st.T = inimg ? 1.0f : 0.0f; st.C0 = st.C1 = st.C2 = 0.0f; st.D = 0.0f; st.Tpre = 1.0f;
     st.nlast = 0;
-    st.N0 = st.N1 = st.N2 = st.L = 0.0f;
+    st.N0 = st.N1 = st.N2 = st.L = st.M = 0.0f;
     for (uint32_t cb = 0; cb < count; cb += CH) {
       const uint32_t nc = (count - cb) < uint32_t(CH) ? (count - cb) : uint32_t(CH);
       stage_chunk<CH, NT, AUX>(S, SA, a, ids, cb, nc, v, o);
@@ -520,6 +525,7 @@ __global__ __launch_bounds__(TS* TS) __attribute__((amdgpu_waves_per_eu(6))) voi
       a.ws.tpre[g] = st.Tpre;
       if (AUX) {
         if (a.dist) a.dist[g] = st.L;
+        if (a.mdepth) a.mdepth[g] = st.M;
         if (a.normal) {
           float* nm = a.normal + 3 * vt.pix_base + local;
           nm[0] = st.N0;

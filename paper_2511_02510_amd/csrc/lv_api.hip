@@ -312,27 +312,27 @@ lv_status lv_query_sizes(lv_context* ctx, const lv_voxels* vox, const lv_frame* 
 static lv_status forward_impl(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
                               const lv_settings* st, void* workspace, void* saved, float* rgb,
                               float* depth, float* alpha, float* wmax, bool aux, float* dist,
-                              float* normal, hipStream_t stream);
+                              float* normal, float* mdepth, hipStream_t stream);
 
 lv_status lv_forward(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
                      const lv_settings* st, void* workspace, void* saved, float* rgb, float* depth,
                      float* alpha, float* wmax, hipStream_t stream) {
   return forward_impl(ctx, vox, frame, st, workspace, saved, rgb, depth, alpha, wmax, false,
-                      nullptr, nullptr, stream);
+                      nullptr, nullptr, nullptr, stream);
 }
 
 lv_status lv_forward_aux(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
                          const lv_settings* st, void* workspace, void* saved, float* rgb,
                          float* depth, float* alpha, float* wmax, float* dist, float* normal,
-                         hipStream_t stream) {
+                         float* mdepth, hipStream_t stream) {
   return forward_impl(ctx, vox, frame, st, workspace, saved, rgb, depth, alpha, wmax, true, dist,
-                      normal, stream);
+                      normal, mdepth, stream);
 }
 
 static lv_status forward_impl(lv_context* ctx, const lv_voxels* vox, const lv_frame* frame,
                               const lv_settings* st, void* workspace, void* saved, float* rgb,
                               float* depth, float* alpha, float* wmax, bool aux, float* dist,
-                              float* normal, hipStream_t stream) {
+                              float* normal, float* mdepth, hipStream_t stream) {
   if (!ctx) return LV_ERR_ARG;
   lv::Layout L;
   lv_status s = validate_all(ctx, vox, frame, st, &L);
@@ -350,6 +350,7 @@ static lv_status forward_impl(lv_context* ctx, const lv_voxels* vox, const lv_fr
   a.wmax = wmax;
   a.dist = dist;
   a.normal = normal;
+  a.mdepth = mdepth;
   {
     PhaseTimer t(ctx, LV_PH_SETUP, stream);
     LV_TRY(lv::launch_setup(a, stream), "setup");   // also zeroes the tile counts
@@ -604,18 +605,22 @@ lv_status lv_l1_grad(lv_context* ctx, const lv_frame* frame, const float* rgb, c
 }
 
 lv_status lv_aux_loss(lv_context* ctx, const lv_frame* frame, const float* depth,
-                      const float* alpha, const float* normal, const float* dist, float lam_tc,
-                      float lam_n, float lam_d, float* loss, float* d_alpha, float* d_depth,
-                      float* d_normal, float* d_dist, hipStream_t stream) {
+                      const float* alpha, const float* normal, const float* dist,
+                      const float* mdepth, float lam_tc, float lam_n, float lam_d, float lam_nm,
+                      float* loss, float* d_alpha, float* d_depth, float* d_normal, float* d_dist,
+                      hipStream_t stream) {
   if (!ctx) return LV_ERR_ARG;
   lv_status s = check_frame(ctx, frame);
   if (s != LV_OK) return s;
   if (!depth || !alpha || !normal || !dist || !loss || !d_alpha || !d_depth || !d_normal ||
       !d_dist)
-    return fail(ctx, LV_ERR_ARG, "lv_aux_loss: every pointer must be non-NULL");
+    return fail(ctx, LV_ERR_ARG, "lv_aux_loss: every pointer but mdepth must be non-NULL");
+  if (lam_nm != 0.0f && !mdepth)
+    return fail(ctx, LV_ERR_ARG, "lv_aux_loss: the median term needs mdepth");
   LV_TRY(lv::run_aux_loss(frame->cams_host, frame->cams_dev, frame->n_views, depth, alpha,
-                          normal, dist, lam_tc, lam_n, lam_d, loss, d_alpha, d_depth, d_normal,
-                          d_dist, stream), "aux_loss");
+                          normal, dist, lam_nm != 0.0f ? mdepth : nullptr, lam_tc, lam_n, lam_d,
+                          lam_nm, loss, d_alpha, d_depth, d_normal, d_dist, stream),
+         "aux_loss");
   return LV_OK;
 }
 

@@ -245,6 +245,7 @@ struct RasterArgs {
   // gradients, each nullable, and the forward's depth, needed with d_dist)
   float* dist;
   float* normal;
+  float* mdepth;   // forward: median depth (no gradient flows through it)
   const float* d_dist;
   const float* d_normal;
   const float* depth_fwd;
@@ -371,9 +372,9 @@ hipError_t launch_fill_set(const FillSet& f, hipStream_t s);
 hipError_t launch_preprocess(const RasterArgs& a, hipStream_t s);
 hipError_t run_aux_loss(const lv_camera* cams_host, const lv_camera* cams_dev, int V,
                         const float* depth, const float* alpha, const float* normal,
-                        const float* dist, float lam_tc, float lam_n, float lam_d, float* loss,
-                        float* g_alpha, float* g_depth, float* g_normal, float* g_dist,
-                        hipStream_t s);
+                        const float* dist, const float* mdepth, float lam_tc, float lam_n,
+                        float lam_d, float lam_nm, float* loss, float* g_alpha, float* g_depth,
+                        float* g_normal, float* g_dist, hipStream_t s);
 hipError_t launch_count_records(const Rec* rec, uint64_t nrec, unsigned long long* out,
                                 hipStream_t s);
 hipError_t launch_scan_tiles(const RasterArgs& a, uint32_t nblk, hipStream_t s);

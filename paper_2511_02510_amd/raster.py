@@ -206,12 +206,13 @@ def backward(ctx, vox, frame, st, workspace, saved, d_rgb, d_depth, d_alpha, d_d
 
 
 def forward_aux(ctx, vox, frame, st, workspace, saved, rgb, depth, alpha, wmax, dist, normal,
-                stream=None):
-    """lv_forward_aux: lv_forward plus the distortion [P] and normal [3P] channels."""
+                mdepth=None, stream=None):
+    """lv_forward_aux: lv_forward plus the distortion [P], normal [3P] and
+    median-depth [P] channels (each may be None)."""
     ctx.check(ctx.lib.lv_forward_aux(ctx.h, ctypes.byref(vox.struct), ctypes.byref(frame.struct),
                                      ctypes.byref(st), _p(workspace), _p(saved), _p(rgb),
                                      _p(depth), _p(alpha), _p(wmax), _p(dist), _p(normal),
-                                     _stream(stream)), "lv_forward_aux")
+                                     _p(mdepth), _stream(stream)), "lv_forward_aux")
 
 
 def backward_aux(ctx, vox, frame, st, workspace, saved, d_rgb, d_depth, d_alpha, depth_fwd,
@@ -224,13 +225,14 @@ def backward_aux(ctx, vox, frame, st, workspace, saved, d_rgb, d_depth, d_alpha,
 
 
 def aux_loss(ctx, frame, depth, alpha, normal, dist, lam_tc, lam_n, lam_d, loss, d_alpha,
-             d_depth, d_normal, d_dist, stream=None):
-    """lv_aux_loss: per-view transmittance-concentration, depth-normal and
-    distortion terms (loss [3 V]) and their gradients."""
+             d_depth, d_normal, d_dist, stream=None, mdepth=None, lam_nm=0.0):
+    """lv_aux_loss: per-view transmittance-concentration, depth-normal,
+    distortion and (with mdepth) median depth-normal terms (loss [4 V]) and
+    their gradients."""
     ctx.check(ctx.lib.lv_aux_loss(ctx.h, ctypes.byref(frame.struct), _p(depth), _p(alpha),
-                                  _p(normal), _p(dist), float(lam_tc), float(lam_n), float(lam_d),
-                                  _p(loss), _p(d_alpha), _p(d_depth), _p(d_normal), _p(d_dist),
-                                  _stream(stream)), "lv_aux_loss")
+                                  _p(normal), _p(dist), _p(mdepth), float(lam_tc), float(lam_n),
+                                  float(lam_d), float(lam_nm), _p(loss), _p(d_alpha), _p(d_depth),
+                                  _p(d_normal), _p(d_dist), _stream(stream)), "lv_aux_loss")
 
 
 def check_overflow(ctx, vox, frame, st, saved, stream=None):
@@ -520,10 +522,11 @@ class Renderer:
 
     def forward(self, rgb, depth, alpha, wmax, vox: Optional[Voxels] = None, stream=None,
                 verify: Optional[bool] = None, saved: Optional[torch.Tensor] = None,
-                dist: Optional[torch.Tensor] = None, normal: Optional[torch.Tensor] = None):
+                dist: Optional[torch.Tensor] = None, normal: Optional[torch.Tensor] = None,
+                mdepth: Optional[torch.Tensor] = None):
         """Returns the saved-state buffer the pass wrote (`saved`, or a larger
         replacement after a capacity re-plan; the renderer's own if None).
-        With dist and/or normal the pass also renders those channels
+        With dist, normal and/or mdepth the pass also renders those channels
         (lv_forward_aux)."""
         vox = vox or self.vox
         own = saved is None
@@ -532,12 +535,12 @@ class Renderer:
         # a truncated pass composites without some occluders, so its weights
         # are not bounded by the true ones: keep w_max to restore on overflow
         keep = wmax.clone() if (verify and wmax is not None) else None
-        aux = dist is not None or normal is not None
+        aux = dist is not None or normal is not None or mdepth is not None
 
         def run(sv):
             if aux:
                 forward_aux(self.ctx, vox, self.frame, self.st, self.workspace, sv, rgb, depth,
-                            alpha, wmax, dist, normal, stream)
+                            alpha, wmax, dist, normal, mdepth, stream)
             else:
                 forward(self.ctx, vox, self.frame, self.st, self.workspace, sv, rgb, depth, alpha,
                         wmax, stream)
@@ -630,8 +633,9 @@ def rasterize(density, sh, renderer: Renderer, wmax: torch.Tensor):
 
 class RasterizeAuxFn(torch.autograd.Function):
     """RasterizeFn with the auxiliary channels: (density, sh) -> (rgb [3P],
-    depth [P], alpha [P], dist [P], normal [3P]).  The node keeps the pass's
-    saved state and its depth (the backward of the distortion reads it)."""
+    depth [P], alpha [P], dist [P], normal [3P], mdepth [P]; mdepth is not
+    differentiable).  The node keeps the pass's saved state and its depth
+    (the backward of the distortion reads it)."""
 
     @staticmethod
     def forward(ctx, density, sh, renderer: Renderer, wmax: torch.Tensor):
@@ -640,16 +644,17 @@ class RasterizeAuxFn(torch.autograd.Function):
         P = renderer.frame.P
         dist = torch.empty(P, device=rgb.device)
         normal = torch.empty(3 * P, device=rgb.device)
+        mdepth = torch.empty(P, device=rgb.device)
         saved = renderer.forward(rgb, depth, alpha, wmax, vox=vox, saved=renderer.new_saved(),
-                                 dist=dist, normal=normal)
+                                 dist=dist, normal=normal, mdepth=mdepth)
         ctx.renderer, ctx.vox, ctx.saved_state = renderer, vox, saved
         ctx.st = renderer.settings_copy()
         ctx.depth = depth.detach().clone()
-        ctx.mark_non_differentiable(wmax)
-        return rgb, depth, alpha, dist, normal
+        ctx.mark_non_differentiable(wmax, mdepth)
+        return rgb, depth, alpha, dist, normal, mdepth
 
     @staticmethod
-    def backward(ctx, g_rgb, g_depth, g_alpha, g_dist, g_normal):
+    def backward(ctx, g_rgb, g_depth, g_alpha, g_dist, g_normal, g_mdepth):
         r, vox = ctx.renderer, ctx.vox
         d_density = torch.empty_like(vox.density)
         d_sh = torch.empty_like(vox.sh)

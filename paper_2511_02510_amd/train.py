@@ -6,7 +6,8 @@ stability guards (Sec. IV-C) followed by priority-driven subdivision
 (Sec. IV-D), after which the optimizer is refreshed (its state is reset, as
 the topology changed).  Optional weights lam_tc, lam_n, lam_d add the
 transmittance-concentration, depth-normal-consistency and distortion terms
-that eq. 6 and eq. 17 name (the library's readings of them) to the objective:
+that eq. 6 and eq. 17 name (the library's readings of them) to the objective,
+and lam_nm its median-based depth-normal term:
 the pass then renders the distortion and normal channels as well, and their
 gradients join the photometric one in a single backward.
 
@@ -54,10 +55,11 @@ class TrainConfig:
     lam_tc: float = 0.0             # transmittance concentration
     lam_n: float = 0.0              # depth-normal consistency
     lam_d: float = 0.0              # ray-space distortion
+    lam_nm: float = 0.0             # median depth-normal consistency
 
     @property
     def aux(self) -> bool:
-        return self.lam_tc != 0.0 or self.lam_n != 0.0 or self.lam_d != 0.0
+        return self.lam_tc != 0.0 or self.lam_n != 0.0 or self.lam_d != 0.0 or self.lam_nm != 0.0
 
 
 def psnr(rgb: torch.Tensor, target: torch.Tensor) -> float:
@@ -82,7 +84,8 @@ class Trainer:
         if cfg.aux:
             self.dist = torch.empty(P, device=self.dev)
             self.normal = torch.empty(3 * P, device=self.dev)
-            self.aux_loss = torch.empty(3 * frame.n_views, device=self.dev)
+            self.mdepth = torch.empty(P, device=self.dev) if cfg.lam_nm else None
+            self.aux_loss = torch.empty(4 * frame.n_views, device=self.dev)
             self.g_alpha, self.g_depth, self.g_dist = (torch.empty(P, device=self.dev)
                                                        for _ in range(3))
             self.g_normal = torch.empty(3 * P, device=self.dev)
@@ -117,17 +120,18 @@ class Trainer:
         gs = torch.empty_like(self.sh)
         if c.aux:
             self.renderer.forward(self.rgb, self.depth, self.alpha, self.wmax, dist=self.dist,
-                                  normal=self.normal)
+                                  normal=self.normal, mdepth=self.mdepth)
             lv.l1_grad(self.ctx, self.frame, self.rgb, self.target, self.weight, self.loss,
                        self.d_rgb)
             lv.aux_loss(self.ctx, self.frame, self.depth, self.alpha, self.normal, self.dist,
                         c.lam_tc, c.lam_n, c.lam_d, self.aux_loss, self.g_alpha, self.g_depth,
-                        self.g_normal, self.g_dist)
+                        self.g_normal, self.g_dist, mdepth=self.mdepth, lam_nm=c.lam_nm)
             # channels whose term has zero weight get no gradient pass
             self.renderer.backward_aux(
                 self.d_rgb, self.g_depth if c.lam_n else None,
-                self.g_alpha if (c.lam_tc or c.lam_n) else None, self.depth,
-                self.g_dist if c.lam_d else None, self.g_normal if c.lam_n else None, gd, gs)
+                self.g_alpha if (c.lam_tc or c.lam_n or c.lam_nm) else None, self.depth,
+                self.g_dist if c.lam_d else None,
+                self.g_normal if (c.lam_n or c.lam_nm) else None, gd, gs)
         else:
             self.renderer.forward(self.rgb, self.depth, self.alpha, self.wmax)
             lv.l1_grad(self.ctx, self.frame, self.rgb, self.target, self.weight, self.loss,

@@ -198,8 +198,8 @@ def test_aux_entry_points_reject_a_null_context():
     vox, fr, st = _vox_frame()
     p = ctypes.c_void_p(0x3000)
     assert lib.lv_forward_aux(None, ctypes.byref(vox), ctypes.byref(fr), ctypes.byref(st), p, p, p,
-                              p, p, p, p, p, None) == _abi.LV_ERR_ARG
+                              p, p, p, p, p, p, None) == _abi.LV_ERR_ARG
     assert lib.lv_backward_aux(None, ctypes.byref(vox), ctypes.byref(fr), ctypes.byref(st), p, p,
                                p, p, p, p, p, p, p, p, None) == _abi.LV_ERR_ARG
-    assert lib.lv_aux_loss(None, ctypes.byref(fr), p, p, p, p, 1.0, 1.0, 1.0, p, p, p, p, p,
-                           None) == _abi.LV_ERR_ARG
+    assert lib.lv_aux_loss(None, ctypes.byref(fr), p, p, p, p, p, 1.0, 1.0, 1.0, 1.0, p, p, p, p,
+                           p, None) == _abi.LV_ERR_ARG

@@ -1,8 +1,14 @@
 """GPU parity of the auxiliary render channels and terms (eq. 6 and 17 name
-them; readings in include/litevoxel.h and oracle/): the distortion and normal
-channels of lv_forward_aux, the adjoint of lv_backward_aux, the image terms of
-lv_aux_loss, and the whole chain channels -> terms -> gradient, against the
-FP64 oracle on the same seeded inputs, through the C-ABI."""
+them; readings in include/litevoxel.h and oracle/): the distortion, normal and
+median-depth channels of lv_forward_aux, the adjoint of lv_backward_aux, the
+image terms of lv_aux_loss, and the whole chain channels -> terms -> gradient,
+against the FP64 oracle on the same seeded inputs, through the C-ABI.
+
+The median depth is the chord midpoint of the hit at which the transmittance
+first reaches 1/2: where the oracle's transmittance after some hit lies
+within 1e-4 of 1/2, binary32 may cross at the neighbouring hit, so the GPU
+value must equal the oracle's median depth at one of the thresholds
+1/2 - 1e-4 and 1/2 + 1e-4 (equal wherever the crossing is clear)."""
 import numpy as np
 import pytest
 
@@ -39,11 +45,26 @@ def _render(ctx, sc, cams, tile=16, chunk=64, chunk_bwd=0, vox=None, bg=(0.0, 0.
     rgb, depth, alpha = r.new_outputs()
     P = frame.P
     dist, normal = torch.empty(P, device=dev), torch.empty(3 * P, device=dev)
+    mdepth = torch.empty(P, device=dev)
     wmax = torch.zeros(vox.n, device=dev)
-    r.forward(rgb, depth, alpha, wmax, dist=dist, normal=normal)
+    r.forward(rgb, depth, alpha, wmax, dist=dist, normal=normal, mdepth=mdepth)
     torch.cuda.synchronize()
     return r, vox, frame, dict(rgb=rgb, depth=depth, alpha=alpha, dist=dist, normal=normal,
-                               wmax=wmax)
+                               wmax=wmax, mdepth=mdepth)
+
+
+def check_mdepth(got, scene, cams):
+    """The GPU median depth against the oracle's crossing band; returns the
+    number of pixels whose crossing lies in the band."""
+    lo = oracle.median_depth(scene, cams, 0.5 + 1e-4)
+    hi = oracle.median_depth(scene, cams, 0.5 - 1e-4)
+    ok = (np.abs(got - lo) <= IMG_TOL) | (np.abs(got - hi) <= IMG_TOL)
+    amb = int(np.count_nonzero(lo != hi))
+    say(f"  median depth: {int(np.count_nonzero(hi))} px with a crossing, {amb} in the band, "
+        f"{int(np.count_nonzero(~ok))} off")
+    assert ok.all()
+    assert amb <= 1e-3 * got.size + 2
+    return amb
 
 
 def _np(t):
@@ -59,6 +80,8 @@ def test_aux_channels_forward(ctx, tile, chunk):
     ref = oracle.render_aux(sc, cams)
     got = {k: _np(v) for k, v in out.items()}
     check_images(got, ref)
+    check_mdepth(got["mdepth"], sc, cams)
+    assert np.count_nonzero(got["mdepth"]) > 300   # pixels where the opacity reaches 1/2
     e_w = float(np.abs(got["wmax"] - ref["wmax"]).max())
     e_l = float(np.abs(got["dist"] - ref["dist"]).max())
     e_n = float(np.abs(got["normal"] - ref["normal"]).max())
@@ -120,15 +143,23 @@ def test_aux_loss_kernel_matches_oracle(ctx):
     normal = rng.normal(0, 0.4, 3 * P)
     dist = rng.uniform(0, 0.05, P)
     lam = (0.3, 0.7, 1.9)
-    L_ref, ga, gd, gn, gl = oaux.aux_losses(depth, alpha, normal, dist, cams, *lam)
+    # a median-depth map: the depth with a bump (a different surface), zeros
+    # where no hit reached one half
+    mdepth = depth + 0.05 * np.cos(np.arange(P) * 0.003)
+    mdepth[rng.random(P) < 0.05] = 0.0
+    depth, alpha, normal, dist, mdepth = (np.asarray(x, np.float32).astype(np.float64)
+                                          for x in (depth, alpha, normal, dist, mdepth))
+    L_ref, ga, gd, gn, gl = oaux.aux_losses(depth, alpha, normal, dist, cams, *lam, mdepth=mdepth,
+                                            lam_nm=1.1)
     dev = ctx.device
     f32 = lambda a: to_dev(a, dev)
-    loss = torch.full((3 * len(cams),), 7.0, device=dev)
+    loss = torch.full((4 * len(cams),), 7.0, device=dev)
     bufs = [torch.full((P,), 9.0, device=dev), torch.full((P,), 9.0, device=dev),
             torch.full((3 * P,), 9.0, device=dev), torch.full((P,), 9.0, device=dev)]
-    lv.aux_loss(ctx, frame, f32(depth), f32(alpha), f32(normal), f32(dist), *lam, loss, *bufs)
+    lv.aux_loss(ctx, frame, f32(depth), f32(alpha), f32(normal), f32(dist), *lam, loss, *bufs,
+                mdepth=f32(mdepth), lam_nm=1.1)
     torch.cuda.synchronize()
-    Lg = _np(loss).reshape(len(cams), 3)
+    Lg = _np(loss).reshape(len(cams), 4)
     say(f"  aux losses GPU {Lg.ravel()} oracle {L_ref.ravel()}")
     assert np.allclose(Lg, L_ref, rtol=1e-4, atol=1e-7)
     for name, g, ref in (("alpha", bufs[0], ga), ("depth", bufs[1], gd), ("normal", bufs[2], gn),
@@ -146,20 +177,22 @@ def test_aux_chain_loss_and_gradient(ctx):
     r, vox, frame, out = _render(ctx, sc, cams, 16, 64)
     lam = (0.05, 0.2, 5.0)
     dev, P = ctx.device, frame.P
-    loss = torch.empty(3 * len(cams), device=dev)
+    loss = torch.empty(4 * len(cams), device=dev)
     ga, gd, gl = (torch.empty(P, device=dev) for _ in range(3))
     gn = torch.empty(3 * P, device=dev)
     lv.aux_loss(ctx, frame, out["depth"], out["alpha"], out["normal"], out["dist"], *lam, loss, ga,
-                gd, gn, gl)
+                gd, gn, gl, mdepth=out["mdepth"], lam_nm=0.3)
     dd, dsh = torch.empty_like(vox.density), torch.empty_like(vox.sh)
     zero_rgb = torch.zeros(3 * P, device=dev)
     r.backward_aux(zero_rgb, gd, ga, out["depth"], gl, gn, dd, dsh)
     torch.cuda.synchronize()
     ref = oracle.render_aux(sc, cams)
     L_ref, ga_r, gd_r, gn_r, gl_r = oaux.aux_losses(ref["depth"], ref["alpha"], ref["normal"],
-                                                    ref["dist"], cams, *lam)
+                                                    ref["dist"], cams, *lam,
+                                                    mdepth=oracle.median_depth(sc, cams),
+                                                    lam_nm=0.3)
     dd_r, dsh_r = oracle.backward_aux(sc, cams, np.zeros(3 * P), gd_r, ga_r, gl_r, gn_r)
-    Lg = _np(loss).reshape(len(cams), 3)
+    Lg = _np(loss).reshape(len(cams), 4)
     say(f"  chain losses GPU {Lg.ravel()} oracle {L_ref.ravel()}")
     assert np.allclose(Lg, L_ref, rtol=1e-3, atol=1e-6)
     e = rel_l2(_np(dd), dd_r)
@@ -179,7 +212,8 @@ def test_aux_autograd_matches_direct_calls(ctx):
     dens = vox.density.clone().requires_grad_(True)
     sh = vox.sh.clone().requires_grad_(True)
     wmax = torch.zeros(vox.n, device=dev)
-    rgb, depth, alpha, dist, normal = lv.rasterize_aux(dens, sh, r, wmax)
+    rgb, depth, alpha, dist, normal, mdepth = lv.rasterize_aux(dens, sh, r, wmax)
+    assert not mdepth.requires_grad
     rng = np.random.default_rng(84)
     P = frame.P
     w = [to_dev(rng.normal(0, s, n), dev) for s, n in ((1e-3, 3 * P), (1e-4, P), (1e-3, P),
@@ -278,14 +312,14 @@ def test_aux_forward_with_one_channel(ctx):
     sc, cams = _scene()
     r, vox, frame, out = _render(ctx, sc, cams, 16, 64)
     P = frame.P
-    for keep in ("dist", "normal"):
+    for keep in ("dist", "normal", "mdepth"):
         rgb, depth, alpha = r.new_outputs()
         wm = torch.zeros(vox.n, device=ctx.device)
-        d = torch.full((P,), 7.0, device=ctx.device) if keep == "dist" else None
-        n = torch.full((3 * P,), 7.0, device=ctx.device) if keep == "normal" else None
-        r.forward(rgb, depth, alpha, wm, dist=d, normal=n)
+        ch = {k: (torch.full(((3 if k == "normal" else 1) * P,), 7.0, device=ctx.device)
+                  if k == keep else None) for k in ("dist", "normal", "mdepth")}
+        r.forward(rgb, depth, alpha, wm, **ch)
         torch.cuda.synchronize()
-        got = d if keep == "dist" else n
+        got = ch[keep]
         assert torch.equal(got, out[keep]), keep
         for k, t in (("rgb", rgb), ("depth", depth), ("alpha", alpha), ("wmax", wm)):
             assert torch.equal(t, out[k]), (keep, k)
@@ -319,12 +353,15 @@ def test_aux_argument_errors(ctx):
     g = torch.zeros(P, device=ctx.device)
     with pytest.raises(lv.LiteVoxelError):   # d_dist without the forward's depth
         r.backward_aux(torch.zeros(3 * P, device=ctx.device), None, None, None, g, None, dd, dsh)
-    loss = torch.empty(3 * frame.n_views, device=ctx.device)
+    loss = torch.empty(4 * frame.n_views, device=ctx.device)
     bufs = [torch.empty(P, device=ctx.device), torch.empty(P, device=ctx.device),
             torch.empty(3 * P, device=ctx.device), torch.empty(P, device=ctx.device)]
-    with pytest.raises(lv.LiteVoxelError):   # every pointer of lv_aux_loss is required
+    with pytest.raises(lv.LiteVoxelError):   # every gradient buffer of lv_aux_loss is required
         lv.aux_loss(ctx, frame, out["depth"], out["alpha"], out["normal"], out["dist"], 1.0, 1.0,
                     1.0, loss, bufs[0], None, bufs[2], bufs[3])
+    with pytest.raises(lv.LiteVoxelError):   # the median term needs the median depth
+        lv.aux_loss(ctx, frame, out["depth"], out["alpha"], out["normal"], out["dist"], 1.0, 1.0,
+                    1.0, loss, *bufs, lam_nm=1.0)
 
 
 def test_aux_step_graph_replays_match_eager(ctx):
@@ -343,7 +380,7 @@ def test_aux_step_graph_replays_match_eager(ctx):
     rgb, depth, alpha = r.new_outputs()
     dist, normal = torch.empty(P, device=dev), torch.empty(3 * P, device=dev)
     wmax = torch.zeros(vox.n, device=dev)
-    loss = torch.empty(3 * V, device=dev)
+    loss = torch.empty(4 * V, device=dev)
     ga, gd, gl = (torch.empty(P, device=dev) for _ in range(3))
     gn = torch.empty(3 * P, device=dev)
     d_rgb = to_dev(np.random.default_rng(90).normal(0, 1e-3, 3 * P), dev)
