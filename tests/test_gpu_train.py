@@ -46,7 +46,7 @@ def test_training_loop_converges_and_adapts(ctx, mode):
 
 
 def test_training_step_with_aux_terms_matches_oracle_chain(ctx):
-    """One trainer step with the photometric and the three auxiliary terms:
+    """One trainer step with the photometric and the four auxiliary terms:
     the objective and the gradient handed to Adam against the oracle chain
     (LF weight -> weighted L1 -> auxiliary terms -> one adjoint pass)."""
     import torch
@@ -64,7 +64,7 @@ def test_training_step_with_aux_terms_matches_oracle_chain(ctx):
     target = rng.uniform(0, 1, 3 * P)
     dev = ctx.device
     frame = lv.Frame(cams, dev)
-    lam = dict(lam_tc=0.05, lam_n=0.2, lam_d=5.0)
+    lam = dict(lam_tc=0.05, lam_n=0.2, lam_d=5.0, lam_nm=0.1)
     cfg = train.TrainConfig(iters=10, t0_frac=0.0, t1_frac=0.5, gamma_max=0.6, **lam)
     tr = train.Trainer(ctx, lv.Voxels.from_scene(sc, dev), frame, to_dev(target, dev), cfg)
     it = 3
@@ -86,7 +86,9 @@ def test_training_step_with_aux_terms_matches_oracle_chain(ctx):
         L_ref += lv_
         g_rgb[3 * off[v]:3 * off[v + 1]] = g.ravel()
     La, ga, gdep, gn, gl = oaux.aux_losses(ref["depth"], ref["alpha"], ref["normal"], ref["dist"],
-                                           cams, lam["lam_tc"], lam["lam_n"], lam["lam_d"])
+                                           cams, lam["lam_tc"], lam["lam_n"], lam["lam_d"],
+                                           mdepth=oracle.median_depth(sc, cams),
+                                           lam_nm=lam["lam_nm"])
     L_ref += float(La.sum())
     dd_ref, dsh_ref = oracle.backward_aux(sc, cams, g_rgb, gdep, ga, gl, gn)
     e1, e2 = rel_l2(gd, dd_ref), rel_l2(gs, dsh_ref)
