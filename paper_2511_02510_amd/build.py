@@ -22,6 +22,9 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # the composite kernels' occupancy targets are met where the LDS allows
+    # them; instances whose LDS caps the occupancy lower would warn
+    "-Wno-pass-failed",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
 

@@ -43,7 +43,6 @@ template <int CH>
 struct Stage {
   float rlo[3][CH];   // b - o
   float rhi[3][CH];   // b + e - o
-  float su[3][CH];    // (b - o) / e
   float inve[CH];
   float cf[8][CH];    // trilinear density as a polynomial in (ux, uy, uz)
   float col[3][CH];
@@ -132,7 +131,6 @@ __device__ __forceinline__ void stage_chunk(Stage<CH>& S, StageAux<CH>* SA, cons
       for (int ax = 0; ax < 3; ++ax) {
         S.rlo[ax][k] = bl[ax];
         S.rhi[ax][k] = bl[ax] + e;
-        S.su[ax][k] = bl[ax] * ie;
       }
       S.inve[k] = ie;
       const float s000 = vr.s0.x, s100 = vr.s0.y, s010 = vr.s0.z, s110 = vr.s0.w;
@@ -258,8 +256,9 @@ __device__ __forceinline__ Quad quad(const Stage<CH>& S, int j, const Ray& ray, 
 #pragma unroll
   for (int ax = 0; ax < 3; ++ax) {
     const float du = ray.d[ax] * ie;
-    q.ua[ax] = fmaf(ta, du, -S.su[ax][j]);
-    q.ub[ax] = fmaf(tb, du, -S.su[ax][j]);
+    const float su = S.rlo[ax][j] * ie;   // (b - o) / e, recomputed: LDS is the occupancy limit
+    q.ua[ax] = fmaf(ta, du, -su);
+    q.ub[ax] = fmaf(tb, du, -su);
   }
   const float sa = trilin(S, j, q.ua), sb = trilin(S, j, q.ub);
   q.tau = fmaxf(q.hl * (sa + sb), 0.0f);
@@ -428,11 +427,12 @@ __device__ __forceinline__ float fwd_fragment(const Stage<CH>& S, const StageAux
   return wk;
 }
 
-// at least 6 waves per SIMD: the AUX instances then fit 80 registers without
-// spilling (84 and 5 waves otherwise, 0.56 against 0.53 ms on the ring
-// workload); the plain ones already do
+// Occupancy targets: 6 waves per SIMD for the AUX instances (80 registers,
+// no spills; 84 registers and 5 waves otherwise, 0.56 against 0.53 ms on the
+// ring workload), 8 for the plain ones (64 registers with a few spilled
+// outside the candidate loop; 72 and 7 waves otherwise, 0.458 against 0.424 ms)
 template <int TS, int NW, bool AUX>
-__global__ __launch_bounds__(TS* TS) __attribute__((amdgpu_waves_per_eu(6))) void k_composite_fwd(
+__global__ __launch_bounds__(TS* TS) __attribute__((amdgpu_waves_per_eu(AUX ? 6 : 8))) void k_composite_fwd(
     RasterArgs a) {
   constexpr int NT = TS * TS;
   constexpr int CH = 64 * NW;
@@ -635,8 +635,9 @@ __device__ __forceinline__ void bwd_spread(const Stage<CH>& S, int jj, const flo
 #pragma unroll
   for (int ax = 0; ax < 3; ++ax) {
     const float du = d[ax] * ie;
-    ua[ax] = fmaf(ta, du, -S.su[ax][jj]);
-    ub[ax] = fmaf(tb, du, -S.su[ax][jj]);
+    const float su = S.rlo[ax][jj] * ie;
+    ua[ax] = fmaf(ta, du, -su);
+    ub[ax] = fmaf(tb, du, -su);
   }
   {
     const float x1 = ua[0], y1 = ua[1], z1 = ua[2];
@@ -666,7 +667,7 @@ constexpr int kRing = 128;
 
 template <int CH, bool AUX>
 struct BwdRing {
-  uint32_t key[kRing];   // jj | pixel lane << 16
+  uint16_t key[kRing];   // jj | pixel lane << 8 (jj < 256)
   float gh[kRing], wk[kRing], tm[kRing], hl[kRing];
   float d[64][3];        // unit ray direction of each pixel of the wave
   float gc[64][3];       // dL/dC of each pixel of the wave
@@ -690,8 +691,8 @@ __device__ __forceinline__ void bwd_drain(const Stage<CH>& S, const BwdRing<CH, 
   if (valid) {
     const uint32_t e = (head + lane) & uint32_t(kRing - 1);
     const uint32_t key = R.key[e];
-    const uint32_t p = key >> 16;
-    jj = int(key & 0xFFFFu);
+    const uint32_t p = key >> 8;
+    jj = int(key & 0xFFu);
     const float d[3] = {R.d[p][0], R.d[p][1], R.d[p][2]};
     const float gc[3] = {R.gc[p][0], R.gc[p][1], R.gc[p][2]};
     bwd_spread(S, jj, d, R.gh[e], R.wk[e], gc, R.tm[e], R.hl[e], g);
@@ -708,12 +709,16 @@ __device__ __forceinline__ void bwd_drain(const Stage<CH>& S, const BwdRing<CH, 
   }
 }
 
+// 6 waves per SIMD where the LDS allows it (the plain chunk-64 instances: 80
+// registers, a few spilled outside the sweep; 94 and 5 waves otherwise, 1.255
+// against 1.19 ms on the ring workload)
 template <int TS, int NW, bool AUX>
-__global__ __launch_bounds__(TS* TS) void k_composite_bwd(RasterArgs a) {
+__global__ __launch_bounds__(TS* TS) __attribute__((amdgpu_waves_per_eu(6))) void k_composite_bwd(RasterArgs a) {
   constexpr int NT = TS * TS;
   constexpr int CH = 64 * NW;
   constexpr int BPR = TS / 8;
   constexpr int NV = AUX ? 14 : 11;   // accumulated values per voxel
+  static_assert(CH <= 256, "ring keys hold the chunk position in 8 bits");
   __shared__ Stage<CH> S;
   __shared__ StageAux<AUX ? CH : 64> s_aux;
   StageAux<CH>* SA = AUX ? reinterpret_cast<StageAux<CH>*>(&s_aux) : nullptr;
@@ -834,7 +839,7 @@ __global__ __launch_bounds__(TS* TS) void k_composite_bwd(RasterArgs a) {
               const uint32_t below = __builtin_amdgcn_mbcnt_hi(
                   uint32_t(hb >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(hb), 0u));
               const uint32_t e = (rhead + rcount + below) & uint32_t(kRing - 1);
-              ring.key[e] = uint32_t(jj) | (uint32_t(lane) << 16);
+              ring.key[e] = uint16_t(uint32_t(jj) | (uint32_t(lane) << 8));
               ring.gh[e] = gh;
               ring.wk[e] = wk;
               ring.tm[e] = tm;
