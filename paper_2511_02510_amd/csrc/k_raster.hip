@@ -427,12 +427,13 @@ __device__ __forceinline__ float fwd_fragment(const Stage<CH>& S, const StageAux
   return wk;
 }
 
-// Occupancy targets: 6 waves per SIMD for the AUX instances (80 registers,
-// no spills; 84 registers and 5 waves otherwise, 0.56 against 0.53 ms on the
-// ring workload), 8 for the plain ones (64 registers with a few spilled
-// outside the candidate loop; 72 and 7 waves otherwise, 0.458 against 0.424 ms)
+// Occupancy targets: 7 waves per SIMD for the AUX instances (72 registers,
+// no spills; 84 registers and 5 waves with no target: 0.56 ms on the ring
+// workload, 0.513 at 6 waves, 0.490 at 7), 8 for the plain ones (64
+// registers with a few spilled outside the candidate loop; 72 and 7 waves
+// otherwise, 0.458 against 0.424 ms)
 template <int TS, int NW, bool AUX>
-__global__ __launch_bounds__(TS* TS) __attribute__((amdgpu_waves_per_eu(AUX ? 6 : 8))) void k_composite_fwd(
+__global__ __launch_bounds__(TS* TS) __attribute__((amdgpu_waves_per_eu(AUX ? 7 : 8))) void k_composite_fwd(
     RasterArgs a) {
   constexpr int NT = TS * TS;
   constexpr int CH = 64 * NW;
@@ -757,6 +758,8 @@ __global__ __launch_bounds__(TS* TS) __attribute__((amdgpu_waves_per_eu(6))) voi
     const Ray ray = pixel_ray(cam, px, py);
     const uint64_t s0 = tile_begin(a, gt);
     const uint32_t* ids = a.ws.ids + s0;
+    float* const dden = a.ws.dden;
+    float* const dcol_v = a.ws.dcol + size_t(v) * size_t(a.n) * 3u;   // this view's colour rows
 
     uint32_t nlast = 0;
     BwdState st;
@@ -886,9 +889,9 @@ __global__ __launch_bounds__(TS* TS) __attribute__((amdgpu_waves_per_eu(6))) voi
         // colour gradients stop at the clamp (channels whose raw value <= 0)
         const bool pass = c < 8u || ((S.id[k] >> (kIdBits + (c - 8u))) & 1u);
         if (s != 0.0f && pass) {
-          const size_t id = S.id[k] & kIdMask;
-          float* dst = c < 8u ? &a.ws.dden[8 * id + c]
-                              : &a.ws.dcol[(size_t(v) * size_t(a.n) + id) * 3 + (c - 8u)];
+          // 32-bit offsets: ids are below 2^28
+          const uint32_t id = S.id[k] & kIdMask;
+          float* dst = c < 8u ? dden + (8u * id + c) : dcol_v + (3u * id + (c - 8u));
           unsafeAtomicAdd(dst, s);
         }
       }
