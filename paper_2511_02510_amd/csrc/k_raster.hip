@@ -42,7 +42,7 @@ constexpr float kSmallTau = 0.03125f;
 template <int CH>
 struct Stage {
   float rlo[3][CH];   // b - o
-  float rhi[3][CH];   // b + e - o
+  float edge[CH];     // e (the far planes are b - o + e)
   float inve[CH];
   float cf[8][CH];    // trilinear density as a polynomial in (ux, uy, uz)
   float col[3][CH];
@@ -130,8 +130,8 @@ __device__ __forceinline__ void stage_chunk(Stage<CH>& S, StageAux<CH>* SA, cons
 #pragma unroll
       for (int ax = 0; ax < 3; ++ax) {
         S.rlo[ax][k] = bl[ax];
-        S.rhi[ax][k] = bl[ax] + e;
       }
+      S.edge[k] = e;
       S.inve[k] = ie;
       const float s000 = vr.s0.x, s100 = vr.s0.y, s010 = vr.s0.z, s110 = vr.s0.w;
       const float s001 = vr.s1.x, s101 = vr.s1.y, s011 = vr.s1.z, s111 = vr.s1.w;
@@ -218,9 +218,11 @@ struct Seg {
 
 template <int CH>
 __device__ __forceinline__ Seg slab(const Stage<CH>& S, int j, const Ray& ray) {
-  const float a0 = S.rlo[0][j] * ray.inv[0], b0 = S.rhi[0][j] * ray.inv[0];
-  const float a1 = S.rlo[1][j] * ray.inv[1], b1 = S.rhi[1][j] * ray.inv[1];
-  const float a2 = S.rlo[2][j] * ray.inv[2], b2 = S.rhi[2][j] * ray.inv[2];
+  const float e = S.edge[j];
+  const float l0 = S.rlo[0][j], l1 = S.rlo[1][j], l2 = S.rlo[2][j];
+  const float a0 = l0 * ray.inv[0], b0 = (l0 + e) * ray.inv[0];
+  const float a1 = l1 * ray.inv[1], b1 = (l1 + e) * ray.inv[1];
+  const float a2 = l2 * ray.inv[2], b2 = (l2 + e) * ray.inv[2];
   Seg s;
   s.tn = fmaxf(fmaxf(fminf(a0, b0), fminf(a1, b1)), fmaxf(fminf(a2, b2), 0.0f));
   s.tf = fminf(fminf(fmaxf(a0, b0), fmaxf(a1, b1)), fmaxf(a2, b2));
