@@ -83,12 +83,18 @@ __device__ __forceinline__ void two_prod(float a, float b, float& p, float& e) {
 // (py + .5 - cy) / fy, 1) is therefore carried as unevaluated float pairs
 // and R^T applied in compensated arithmetic: each world component is the
 // correctly rounded sum of its products up to a few ulps of itself, also
-// where the products cancel.  The normalisation then scales all three
-// components alike.  Per pixel, not per fragment.
+// where the products cancel.  The normalisation (hardware reciprocal square
+// root) then scales all three components alike, and the inverse components
+// are hardware reciprocals (about 1 ulp each); the forward and the backward
+// both take their chords from this one function.  Per pixel, not per
+// fragment.
 __device__ __forceinline__ Ray pixel_ray(const lv_camera& c, int px, int py) {
   const float nx = (float(px) + 0.5f) - c.cx, ny = (float(py) + 0.5f) - c.cy;   // exact
-  const float xh = nx / c.fx, yh = ny / c.fy;
-  const float xl = fmaf(-xh, c.fx, nx) / c.fx, yl = fmaf(-yh, c.fy, ny) / c.fy;
+  // hardware reciprocals (about 1 ulp): xh within a few ulps of nx / fx, and
+  // xh + xl equal to it far below the binary32 rounding of the pair's sum
+  const float rfx = __builtin_amdgcn_rcpf(c.fx), rfy = __builtin_amdgcn_rcpf(c.fy);
+  const float xh = nx * rfx, yh = ny * rfy;
+  const float xl = fmaf(-xh, c.fx, nx) * rfx, yl = fmaf(-yh, c.fy, ny) * rfy;
   float dd[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -100,14 +106,14 @@ __device__ __forceinline__ Ray pixel_ray(const lv_camera& c, int px, int py) {
     const float low = ((e1 + e2) + (e3 + e4)) + (c.R[a] * xl + c.R[3 + a] * yl);
     dd[a] = s2 + low;
   }
-  const float in = 1.0f / sqrtf(dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2]);
+  const float in = __builtin_amdgcn_rsqf(dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2]);
   Ray r;
   r.d[0] = dd[0] * in; r.d[1] = dd[1] * in; r.d[2] = dd[2] * in;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     float x = r.d[a];
     if (fabsf(x) < 1e-30f) x = x < 0.0f ? -1e-30f : 1e-30f;
-    r.inv[a] = 1.0f / x;
+    r.inv[a] = __builtin_amdgcn_rcpf(x);
   }
   return r;
 }
