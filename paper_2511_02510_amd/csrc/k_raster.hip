@@ -435,8 +435,8 @@ __device__ __forceinline__ float fwd_fragment(const Stage<CH>& S, const StageAux
   return wk;
 }
 
-// Occupancy targets: 7 waves per SIMD for the AUX instances (72 registers,
-// no spills; 84 registers and 5 waves with no target: 0.56 ms on the ring
+// Occupancy targets: 7 waves per SIMD for the AUX instances (at most 72
+// registers, no spills; 84 registers and 5 waves with no target: 0.56 ms on the ring
 // workload, 0.513 at 6 waves, 0.490 at 7), 8 for the plain ones (64
 // registers with a few spilled outside the candidate loop; 72 and 7 waves
 // otherwise, 0.458 against 0.424 ms)
