@@ -93,6 +93,12 @@ def test_validation_rejects_bad_arguments():
     fr.n_views = 0
     assert v() == _abi.LV_ERR_ARG
     fr.n_views = 1
+    # the view count's upper bound: LV_MAX_VIEWS frames pass, one more fails
+    vm, fm, sm = _vox_frame(views=_abi.LV_MAX_VIEWS + 1)
+    fm.n_views = _abi.LV_MAX_VIEWS
+    assert lib.lv_validate(ctypes.byref(vm), ctypes.byref(fm), ctypes.byref(sm)) == _abi.LV_OK
+    fm.n_views = _abi.LV_MAX_VIEWS + 1
+    assert lib.lv_validate(ctypes.byref(vm), ctypes.byref(fm), ctypes.byref(sm)) == _abi.LV_ERR_ARG
     fr._keep[0].width = 0
     assert v() == _abi.LV_ERR_ARG
     fr._keep[0].width = 64
