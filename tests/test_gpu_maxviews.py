@@ -146,3 +146,35 @@ def test_max_views_loss_weight_l1_and_depth_quantile(ctx, problem):
     assert np.array_equal(bins.cpu().numpy(), qref["bins"])
     assert np.array_equal(tau.cpu().numpy(), qref["tau"])
     assert np.array_equal(prune.cpu().numpy(), qref["prune"])
+
+
+def _strip_camera(o, width, height):
+    """A view of the largest side the ABI takes in one direction and a few
+    pixels in the other, with square pixels and the usual field of view
+    along the long side (a thin strip through the scene)."""
+    c = look_at(o, width, height)
+    foc = c.fx if width >= height else look_at(o, height, width).fx
+    return synth.Camera(R=c.R, o=c.o, fx=foc, fy=foc, cx=width / 2.0, cy=height / 2.0,
+                        width=width, height=height)
+
+
+def test_max_image_sides(ctx):
+    # 32767 x 3 and 3 x 32767 pixels (the side limit): pixel coordinates and
+    # ranges at the top of their 16-bit fields, rows of 4096 tiles at tile 8
+    scene = small_shell(6000, seed=155, deg=1, lmin=4, lmax=7, clutter=0.2)
+    cams = [_strip_camera((2.1, 0.63, 1.37), 32767, 3), _strip_camera((-1.4, 0.91, 2.03), 3, 32767),
+            look_at((0.7, -2.2, 1.1), 33, 21)]
+    P = sum(c.npix for c in cams)
+    say("views of 32767 x 3, 3 x 32767 and 33 x 21 px: keys, forward, backward")
+    grads = random_grads(np.random.default_rng(156), P)
+    ref = oracle.render(scene, cams)
+    assert ref["alpha"][:cams[0].npix].max() > 0.1 and ref["alpha"][cams[0].npix:].max() > 0.1
+    dd, dsh = oracle.backward(scene, cams, *grads)
+    for tile in (8, 32):
+        g = run_gpu(ctx, scene, cams, tile=tile, chunk=64, grads=grads)
+        check_keys(g["bins"], scene, cams, tile)
+        check_images(g, ref)
+        assert np.abs(g["wmax"] - ref["wmax"]).max() <= WMAX_TOL
+        e1, e2 = rel_l2(g["dd"], dd), rel_l2(g["dsh"], dsh)
+        say(f"  tile {tile}: gradient rel-L2 density {e1:.2e} sh {e2:.2e}")
+        assert e1 <= GRAD_TOL and e2 <= GRAD_TOL
