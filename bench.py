@@ -33,7 +33,7 @@ def log(*a):
 
 
 # algorithmic bytes per launch of the composite kernels, the per-unit figures
-# of the hot-path byte model (DESIGN.md section 5): per (tile, voxel) pair 4 B
+# of the hot-path byte model: per (tile, voxel) pair 4 B
 # id + a 59 B record gather (forward), plus 11 reduced 4-byte gradients
 # (backward: 107 B); per pixel 28 B (forward: rgb 12 + depth 4 + alpha 4 +
 # saved state 8; backward: saved state 8 + rgb/depth/alpha gradients 20).
@@ -97,8 +97,8 @@ def counter_valu(kernel, tile, chunk, ms):
             "peak_wave_instr_per_s": VALU_PEAK, "lane_util": float(t[4])}
 
 
-# SURVEY-style algorithmic bytes of the whole forward and backward (all
-# phases): N voxels, M visible (view, voxel) records, Q pairs, P pixels,
+# algorithmic bytes of the whole forward and backward (all phases), each
+# byte the method must move counted once: N voxels, M visible (view, voxel) records, Q pairs, P pixels,
 # K SH floats per voxel
 def step_bytes(N, M, Q, P, K):
     b_fwd = N * (7 + 32 + 4 * K) + 4 * N + 20 * M + 91 * Q + 28 * P
