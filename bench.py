@@ -259,7 +259,7 @@ def main():
         return
 
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (--gpus {args.gpus} requested): this build "
+        print(f"bench.py measures one GPU only (--gpus {args.gpus} requested): the library "
               "has no multi-GPU path; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
