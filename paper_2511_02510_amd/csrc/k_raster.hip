@@ -678,37 +678,56 @@ template <int CH, bool AUX>
 struct BwdRing {
   uint16_t key[kRing];   // jj | pixel lane << 8 (jj < 256)
   float gh[kRing], wk[kRing], tm[kRing], hl[kRing];
-  float d[64][3];        // unit ray direction of each pixel of the wave
-  float gc[64][3];       // dL/dC of each pixel of the wave
-  float gn[AUX ? 64 : 1][3];   // AUX: dL/dN of each pixel of the wave
+  // plain instances: the unit ray direction and dL/dC of each pixel of the
+  // wave; the AUX instances read those (and dL/dN) from the pixel's own lane
+  // instead, which leaves them the LDS for one more wave per SIMD
+  float d[AUX ? 1 : 64][3];
+  float gc[AUX ? 1 : 64][3];
 };
 
 // Processes the `count` (<= 64) oldest entries of the ring with one entry per
 // lane: corner and colour contributions, summed over runs of lanes on the
 // same voxel, added to the chunk's LDS accumulators.  Every lane of the
 // wave must call it.
+// own (AUX): this lane's pixel values (unit ray direction, dL/dC, dL/dN),
+// read by the entries of that pixel through a cross-lane permute.
 template <int CH, bool AUX>
 __device__ __forceinline__ void bwd_drain(const Stage<CH>& S, const BwdRing<CH, AUX>& R,
-                                          double (*s_g)[CH], uint32_t head, uint32_t count) {
+                                          double (*s_g)[CH], uint32_t head, uint32_t count,
+                                          const float (&own)[9]) {
   constexpr int NV = AUX ? 14 : 11;
   const uint32_t lane = threadIdx.x & 63u;
   const bool valid = lane < count;
   int jj = 0;
+  uint32_t p = lane, e = 0u;
+  if (valid) {
+    e = (head + lane) & uint32_t(kRing - 1);
+    const uint32_t key = R.key[e];
+    p = key >> 8;
+    jj = int(key & 0xFFu);
+  }
+  float pv[9];
+  if constexpr (AUX) {   // every lane takes part in the permute
+#pragma unroll
+    for (int c = 0; c < 9; ++c)
+      pv[c] = __int_as_float(__builtin_amdgcn_ds_bpermute(int(p << 2), __float_as_int(own[c])));
+  }
   float g[NV];
 #pragma unroll
   for (int c = 0; c < NV; ++c) g[c] = 0.0f;
   if (valid) {
-    const uint32_t e = (head + lane) & uint32_t(kRing - 1);
-    const uint32_t key = R.key[e];
-    const uint32_t p = key >> 8;
-    jj = int(key & 0xFFu);
-    const float d[3] = {R.d[p][0], R.d[p][1], R.d[p][2]};
-    const float gc[3] = {R.gc[p][0], R.gc[p][1], R.gc[p][2]};
-    bwd_spread(S, jj, d, R.gh[e], R.wk[e], gc, R.tm[e], R.hl[e], g);
-    if (AUX) {   // dL/dn of the voxel: w times the pixel's dL/dN
-      g[11] = R.wk[e] * R.gn[p][0];
-      g[12] = R.wk[e] * R.gn[p][1];
-      g[13] = R.wk[e] * R.gn[p][2];
+    if constexpr (AUX) {
+      const float d[3] = {pv[0], pv[1], pv[2]};
+      const float gc[3] = {pv[3], pv[4], pv[5]};
+      bwd_spread(S, jj, d, R.gh[e], R.wk[e], gc, R.tm[e], R.hl[e], g);
+      // dL/dn of the voxel: w times the pixel's dL/dN
+      g[NV - 3] = R.wk[e] * pv[6];
+      g[NV - 2] = R.wk[e] * pv[7];
+      g[NV - 1] = R.wk[e] * pv[8];
+    } else {
+      const float d[3] = {R.d[p][0], R.d[p][1], R.d[p][2]};
+      const float gc[3] = {R.gc[p][0], R.gc[p][1], R.gc[p][2]};
+      bwd_spread(S, jj, d, R.gh[e], R.wk[e], gc, R.tm[e], R.hl[e], g);
     }
   }
   const bool last = seg_reduce_rows<NV>(g, jj, valid);
@@ -720,9 +739,11 @@ __device__ __forceinline__ void bwd_drain(const Stage<CH>& S, const BwdRing<CH, 
 
 // 6 waves per SIMD where the LDS allows it (the plain chunk-64 instances: 80
 // registers, a few spilled outside the sweep; 94 and 5 waves otherwise, 1.255
-// against 1.19 ms on the ring workload)
+// against 1.19 ms on the ring workload), 5 for the AUX ones (96 registers, no
+// spills; with the pixel values taken from the owning lanes their chunk-64
+// LDS fits 5 workgroups: 1.60 against 1.52 ms)
 template <int TS, int NW, bool AUX>
-__global__ __launch_bounds__(TS* TS) __attribute__((amdgpu_waves_per_eu(6))) void k_composite_bwd(RasterArgs a) {
+__global__ __launch_bounds__(TS* TS) __attribute__((amdgpu_waves_per_eu(AUX ? 5 : 6))) void k_composite_bwd(RasterArgs a) {
   constexpr int NT = TS * TS;
   constexpr int CH = 64 * NW;
   constexpr int BPR = TS / 8;
@@ -797,11 +818,16 @@ __global__ __launch_bounds__(TS* TS) __attribute__((amdgpu_waves_per_eu(6))) voi
         }
       }
     }
-    // the wave's rays and colour gradients, read back by the deferred part
-    ring.d[lane][0] = ray.d[0]; ring.d[lane][1] = ray.d[1]; ring.d[lane][2] = ray.d[2];
-    ring.gc[lane][0] = st.gC0; ring.gc[lane][1] = st.gC1; ring.gc[lane][2] = st.gC2;
-    if (AUX) {
-      ring.gn[lane][0] = st.gN0; ring.gn[lane][1] = st.gN1; ring.gn[lane][2] = st.gN2;
+    // the pixel's values the deferred part reads: in the wave's LDS (plain
+    // instances) or from this lane's registers (AUX)
+    float own[9];
+    if constexpr (AUX) {
+      own[0] = ray.d[0]; own[1] = ray.d[1]; own[2] = ray.d[2];
+      own[3] = st.gC0; own[4] = st.gC1; own[5] = st.gC2;
+      own[6] = st.gN0; own[7] = st.gN1; own[8] = st.gN2;
+    } else {
+      ring.d[lane][0] = ray.d[0]; ring.d[lane][1] = ray.d[1]; ring.d[lane][2] = ray.d[2];
+      ring.gc[lane][0] = st.gC0; ring.gc[lane][1] = st.gC1; ring.gc[lane][2] = st.gC2;
     }
     if (nlast) atomicMax(&s_maxn, nlast);
     __syncthreads();
@@ -858,7 +884,7 @@ __global__ __launch_bounds__(TS* TS) __attribute__((amdgpu_waves_per_eu(6))) voi
             }
             rcount += uint32_t(__popcll(hb));
             if (rcount >= 64u) {
-              bwd_drain(S, ring, s_g, rhead, 64u);
+              bwd_drain(S, ring, s_g, rhead, 64u, own);
               rhead = (rhead + 64u) & uint32_t(kRing - 1);
               rcount -= 64u;
             }
@@ -866,7 +892,7 @@ __global__ __launch_bounds__(TS* TS) __attribute__((amdgpu_waves_per_eu(6))) voi
         }
       }
       if (rcount) {   // the rest of this chunk's fragments
-        bwd_drain(S, ring, s_g, rhead, rcount);
+        bwd_drain(S, ring, s_g, rhead, rcount, own);
         rhead = (rhead + rcount) & uint32_t(kRing - 1);
         rcount = 0u;
       }
