@@ -40,9 +40,9 @@
  *     that every call may overwrite.  Each pass that will be differentiated
  *     later keeps its own `saved`; one workspace serves them all.
  *   - All device work is enqueued on the given stream; no call below
- *     synchronises except lv_check_overflow, lv_export_bins, lv_autotune
- *     and lv_read_timings, which say so.  The enqueuing calls allocate no
- *     device memory and can be captured into a HIP graph.
+ *     synchronises except lv_check_overflow, lv_pass_stats, lv_export_bins,
+ *     lv_autotune and lv_read_timings, which say so.  The enqueuing calls
+ *     allocate no device memory and can be captured into a HIP graph.
  *   - Errors: every call returns an lv_status.  Argument errors are detected
  *     on the host before anything is enqueued (LV_ERR_ARG); a HIP runtime or
  *     launch failure gives LV_ERR_HIP.  lv_last_error() returns a message for
